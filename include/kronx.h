@@ -1,0 +1,200 @@
+/*
+ * kronx -- exact-exchange application Vx.psi on one AMD MI355X (gfx950)
+ * through a batched Kronecker-product Poisson solver.
+ *
+ * Operation (arXiv 2501.16572):
+ *   Eq. (Vx:Poisson)  Vx phi_n = - sum_m w g_m psi_m (.) phi_mn, where
+ *   Eq. (Poisson)     -(1/4 pi) L phi_mn = conj(psi_m) (.) phi_n   (unscreened), or
+ *   Eq. (Poisson:SR)  the screened counterpart (erfc(omega r)/r interaction),
+ *   solved as Eq. (LS:Discrete:Solution) X = f(L) B with f of Eq. (fL) and the
+ *   Kronecker eigendecomposition of Eq. (FinalRepfL), L = (V1 (x) V2 (x) V3)
+ *   Lambda (...)^H, applied to a batch of right-hand sides at once (Sec. II.B).
+ *   The screened kernel is f(lambda) = -(4 pi/lambda)(1 - exp(lambda/(4 omega^2)))
+ *   (the erfc(omega r)/r interaction; the exponent printed in Eq. (fL) is
+ *   read this way), with the zero mode f(0) = pi/omega^2; unscreened
+ *   f(lambda) = -4 pi/lambda with f(0) = 0 (zero-mean solution).
+ *
+ * Conventions shared by every call:
+ *   - Grid: n1 x n2 x n3 uniform points, flat index i1 + n1*(i2 + n2*i3) (x1
+ *     fastest; B(:,:,k) is the k-th frontal slice, Sec. II.A).  Units: bohr,
+ *     Hartree.
+ *   - A set of grid functions is column-major: column j starts at
+ *     base + j*ld elements, ld >= N = n1*n2*n3.
+ *   - Element types follow the plan's precision: KX_PREC_FP64 -> double;
+ *     KX_PREC_FP32 / KX_PREC_BF16X3 / KX_PREC_BF16X6 -> float.  Plans with a
+ *     nonzero Bloch wavevector are complex: interleaved (re, im) pairs of that
+ *     type.  Outputs of exx_apply are always double (complex: (re, im)
+ *     doubles): they accumulate in FP64.
+ *   - Pointers named d_* are device pointers (hipMalloc'd or torch CUDA
+ *     tensors) owned by the caller; the library never frees them.  Host
+ *     pointers are read during the call only.
+ *   - Every call that takes a stream enqueues work on that hipStream_t (passed
+ *     as void*; NULL = the default stream) and returns without waiting.
+ *   - Errors: every call returns a kx_status.  Argument errors are detected
+ *     before any work is enqueued (nothing is modified).  A device error
+ *     surfaces as KX_EDEVICE from the call that observes it.  kx_last_error()
+ *     returns this thread's text for the last non-OK status.  No call aborts
+ *     or throws across this boundary.
+ */
+#ifndef KRONX_H
+#define KRONX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kx_plan_s* kx_plan;
+
+typedef enum {
+  KX_OK = 0,
+  KX_EINVAL = 1,        /* invalid argument (null pointer, bad size, ld < N, ...) */
+  KX_EUNSUPPORTED = 2,  /* valid but not implemented (e.g. an axis longer than 160) */
+  KX_ENOMEM = 3,        /* device or host allocation failed */
+  KX_EDEVICE = 4,       /* HIP runtime error */
+  KX_ESTATE = 5         /* call not valid in the current state */
+} kx_status;
+
+/* Boundary condition per axis (Sec. II): periodic (Bloch-periodic when the
+ * axis' component of the wavevector k - q is nonzero) along extended
+ * directions, zero Dirichlet along vacuum directions (n interior nodes, the
+ * wall one spacing beyond each end node). */
+enum { KX_BC_PERIODIC = 0, KX_BC_DIRICHLET = 1 };
+
+/* Arithmetic of the mode products (the dense matrix products of Sec. II.B).
+ * The 1D eigendecompositions, the f(Lambda~) table, the eigen-scaling
+ * multiply, the Vx accumulation and the E_x reduction are FP64 in all modes.
+ *   FP64   : FP64 MFMA, FP64 intermediates.
+ *   FP32   : FP32 MFMA with FP32 accumulation, FP32 intermediates.
+ *   BF16X3 : each FP32 operand split into bf16 hi + lo; hi*hi + hi*lo + lo*hi
+ *            on bf16 MFMA with FP32 accumulation.
+ *   BF16X6 : three-way split hi + mid + lo, the six products down to
+ *            relative weight 2^-16. */
+enum { KX_PREC_FP64 = 0, KX_PREC_FP32 = 1, KX_PREC_BF16X3 = 2, KX_PREC_BF16X6 = 3 };
+
+/* Kernel organisation for exx_apply / kron_solve.
+ *   FUSED : three passes per batch -- (A) pair density + mode-1 + mode-2
+ *           forward on frontal slices, (B) mode-3 forward, eigen-scaling,
+ *           mode-3 inverse on x3 pencils, (C) mode-2 + mode-1 inverse, the
+ *           psi_m product and the accumulation into Vx, with E_x partials.
+ *   PLAIN : one kernel per step (pair density, three forward mode products,
+ *           scaling, three inverse mode products, accumulation), each a full
+ *           pass over the batch in device memory.  FP64 only. */
+enum { KX_PATH_FUSED = 0, KX_PATH_PLAIN = 1 };
+
+/* kron_setup -- build a plan for X = f(L) B on one grid (Sec. II.A,
+ * Eqs. (fL), (FinalRepfL)).
+ *   n[3]      grid points per axis, 1 <= n_d <= 160.
+ *   h[3]      grid spacing per axis (bohr), > 0.
+ *   bc[3]     KX_BC_PERIODIC or KX_BC_DIRICHLET per axis.
+ *   fd_order  even order of the central second-derivative stencil, 2..16.
+ *   omega     screening parameter (bohr^-1); <= 0 selects the unscreened
+ *             Coulomb kernel.
+ *   kq[3]     Bloch wavevector k - q (bohr^-1) per axis, or NULL for zero.
+ *             A nonzero component requires a periodic axis and makes the
+ *             plan complex.
+ *   prec      KX_PREC_*.
+ *   out       receives the plan.  On error *out is set to NULL.
+ * Host-side FP64 work (weights, eigenpairs, f table), then device uploads on
+ * the current device (synchronous).  The plan is immutable afterwards and may
+ * be used from several streams, but its internal workspace is shared: calls
+ * on different streams must not overlap in time. */
+kx_status kron_setup(const int n[3], const double h[3], const int bc[3], int fd_order,
+                     double omega, const double kq[3], int prec, kx_plan* out);
+
+/* kron_destroy -- release a plan (waits for the device).  NULL is a no-op. */
+kx_status kron_destroy(kx_plan p);
+
+/* kron_solve -- X = f(L) B for nrhs right-hand sides (Sec. II.B, Eq.
+ * (LS:Discrete:Solution:Block)).
+ *   d_B  nrhs columns, leading dimension ldb >= N, plan element type.
+ *   d_X  nrhs columns, leading dimension ldx >= N, plan element type;
+ *        overwritten.  d_X may not overlap d_B.
+ *   path KX_PATH_*. */
+kx_status kron_solve(kx_plan p, const void* d_B, int64_t ldb, void* d_X, int64_t ldx,
+                     int nrhs, int path, void* stream);
+
+/* exx_apply -- Vx phi_n for n = 0..n_b-1, Eqs. (Vx:Poisson), (W):
+ *   d_vx[:, n] += - sum_{m < n_occ} d_occ[m] * psi_m (.) phi_mn,
+ *   phi_mn = f(L) (conj(psi_m) (.) phi_n).
+ *   d_psi    occupied orbitals psi_m (at q), n_occ columns, leading dim ld_psi.
+ *   d_occ    n_occ doubles (device): the weights w_q * g_mq.
+ *   d_phi    the functions the operator is applied to (at k), n_b columns,
+ *            leading dim ld_phi.  May alias d_psi.
+ *   d_vx     n_b columns of doubles (complex plans: (re, im) doubles),
+ *            leading dim ld_vx; ACCUMULATED (+=), so callers may loop over q
+ *            and over batches.
+ *   d_ex     one device double, ACCUMULATED: += dV * sum_n d_gphi[n] *
+ *            Re <phi_n, Delta vx_n>, where Delta vx_n is this call's
+ *            contribution; with phi = psi at one k and d_gphi = g_n * w_k this
+ *            is the exchange energy E_x = sum_n g_n Re <psi_n, Vx psi_n> dV.
+ *            May be NULL (then d_gphi is ignored).
+ *   d_gphi   n_b doubles (device) or NULL when d_ex is NULL.
+ *   path     KX_PATH_*.
+ * Work: n_b * n_occ Poisson solves.  The reduction order is fixed, so two
+ * identical calls give bitwise identical results. */
+kx_status exx_apply(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, const double* d_occ,
+                    const void* d_phi, int64_t ld_phi, int n_b, double* d_vx, int64_t ld_vx,
+                    double* d_ex, const double* d_gphi, int path, void* stream);
+
+/* One unit of a batched call: an exx_apply with its own plan.  Field
+ * meanings are those of exx_apply's arguments. */
+typedef struct {
+  kx_plan plan;
+  const void* d_psi;
+  int64_t ld_psi;
+  int n_occ;
+  const double* d_occ;
+  const void* d_phi;
+  int64_t ld_phi;
+  int n_b;
+  double* d_vx;
+  int64_t ld_vx;
+  double* d_ex;
+  const double* d_gphi;
+} kx_task;
+
+/* exx_apply_batched -- run ntasks exx_apply units (several k-point pairs and
+ * several systems of uneven grid sizes) as one captured HIP graph on
+ * `stream`.  The first call with a given task list captures the graph; later
+ * calls with the same plans, pointers and sizes replay it.  Tasks writing the
+ * same d_vx / d_ex are applied in task order.  All plans must share one
+ * precision. */
+kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream);
+
+/* kx_plan_info -- sizes the plan chose (for reports and tests).
+ *   out[0..2]  n1, n2, n3           out[3]  complex flag
+ *   out[4]     precision            out[5]  padded slice size (x1, x2)
+ *   out[6]     padded pencil size (x3)
+ *   out[7]     target bands per batch the last exx_apply used (0 before any) */
+kx_status kx_plan_info(kx_plan p, int64_t out[8]);
+
+/* kx_plan_tables -- copy the plan's host FP64 tables (no device work).
+ *   axis 0..2: lam (n_d doubles, ascending) and the eigenvectors as V[k*n + a]
+ *   = component k of eigenvector a (V_re, V_im; V_im may be NULL for real
+ *   plans).  axis = 3: lam receives the N-entry f(Lambda~) table in the flat
+ *   grid order (V_re, V_im ignored). Any output pointer may be NULL. */
+kx_status kx_plan_tables(kx_plan p, int axis, double* lam, double* V_re, double* V_im);
+
+/* kx_host_eig1d -- host only, no device use: the 1D second-derivative
+ * operator's eigenpairs exactly as kron_setup computes them (for tests of the
+ * host plan).  lam: n doubles; V_re, V_im: n*n doubles each, V[k*n + a]
+ * (V_im may be NULL when kappa == 0 or bc is Dirichlet). */
+kx_status kx_host_eig1d(int n, double h, int bc, int fd_order, double kappa, double* lam,
+                        double* V_re, double* V_im);
+
+/* kx_host_fd_weights -- host only: the weights c_0..c_p (p = fd_order/2) of
+ * the central second-derivative stencil, f'' ~ sum_s c_|s| f(x + s h) / h^2. */
+kx_status kx_host_fd_weights(int fd_order, double* c);
+
+/* kx_last_error -- text for this thread's last non-OK status ("" if none).
+ * The pointer stays valid until the next call on this thread. */
+const char* kx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRONX_H */

@@ -1,0 +1,586 @@
+// C ABI of the library: plans, exx_apply, kron_solve, batched graph replay.
+//
+// Work per exx_apply (arXiv 2501.16572, Eq. (Vx:Poisson) with the batch
+// Kronecker solve of Sec. II.B): the n_b x n_occ pair solves are cut into
+// batches of n_t target columns x all n_occ occupied columns; one batch's
+// pair intermediates live in a plan-owned device workspace and go through
+//   pass A  pair density + forward modes 1, 2        (k_slice_fwd)
+//   pass B  forward mode 3, f(Lambda~), inverse mode 3 (k_pencil)
+//   pass C  inverse modes 2, 1, psi_m product, Vx accumulation, E_x partials
+//   finalize  fixed-order FP64 reduction of the E_x partials into *ex.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/kronx.h"
+#include "launch.h"
+#include "plan_host.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+kx_status fail(kx_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+kx_status dev_fail(hipError_t e, const char* what) {
+  return fail(KX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int elem_bytes(int prec) { return prec == KX_PREC_FP64 ? 8 : 4; }
+
+}  // namespace
+
+namespace kx {
+
+int device_cu_count() {
+  static std::mutex mu;
+  static std::vector<int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (cache[dev] == 0) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1)
+      cu = 1;
+    cache[dev] = cu;
+  }
+  return cache[dev];
+}
+
+// *ex += dV * sum_t gphi[t] * sum_j partials[t*per_target + j], fixed order.
+__global__ void __launch_bounds__(256)
+k_ex_finalize(const double* partials, int n_t, int per_target, const double* gphi, double dV,
+              double* ex) {
+  __shared__ double red[256];
+  double s = 0.0;
+  const int total = n_t * per_target;
+  for (int i = threadIdx.x; i < total; i += blockDim.x) s += gphi[i / per_target] * partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *ex += dV * red[0];
+}
+
+hipError_t launch_ex_finalize(const double* partials, int n_t, int per_target, const double* gphi,
+                              double dV, double* ex, hipStream_t s) {
+  hipLaunchKernelGGL(k_ex_finalize, dim3(1), dim3(256), 0, s, partials, n_t, per_target, gphi, dV,
+                     ex);
+  return hipGetLastError();
+}
+
+}  // namespace kx
+
+struct kx_graph_entry {
+  std::vector<kx_task> tasks;
+  std::vector<unsigned> generations;  // workspace generation of each task's plan at capture
+  hipStream_t stream;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+struct kx_plan_s {
+  int n[3];
+  double h[3];
+  int bc[3];
+  int order;
+  double omega;
+  double kq[3];
+  int prec;
+  bool cplx;
+  int64_t N;
+  int n12;
+  double dV;
+  std::vector<double> lam[3], Vre[3], Vim[3], f;
+  int nk12, nk3, P12, P3;
+  int device;
+  void* dVmat[3] = {nullptr, nullptr, nullptr};
+  double* d_f = nullptr;
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  double* d_part = nullptr;
+  size_t part_bytes = 0;
+  int last_nt = 0;
+  int max_blocks = 0;    // 0: as many as are co-resident
+  unsigned ws_gen = 0;   // bumped whenever a device buffer is reallocated
+};
+
+namespace {
+
+std::mutex g_graph_mu;
+std::vector<kx_graph_entry> g_graphs;
+
+size_t workspace_limit() {
+  const char* env = std::getenv("KX_WORKSPACE_MB");
+  if (env && *env) {
+    long long mb = std::atoll(env);
+    if (mb > 0) return (size_t)mb << 20;
+  }
+  size_t free_b = 0, total_b = 0;
+  size_t lim = (size_t)32 << 30;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
+    lim = std::min(lim, free_b / 5 * 2);
+  return std::max(lim, (size_t)64 << 20);
+}
+
+kx_status ensure_buffer(void** ptr, size_t* have, size_t need, const char* what) {
+  if (*have >= need && *ptr) return KX_OK;
+  if (*ptr) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return dev_fail(e, "synchronize before regrow");
+    hipFree(*ptr);
+    *ptr = nullptr;
+    *have = 0;
+  }
+  hipError_t e = hipMalloc(ptr, need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return fail(KX_ENOMEM, "cannot allocate %zu bytes of %s", need, what);
+  }
+  *have = need;
+  return KX_OK;
+}
+
+void free_plan_device(kx_plan p) {
+  for (int d = 0; d < 3; ++d)
+    if (p->dVmat[d]) hipFree(p->dVmat[d]);
+  if (p->d_f) hipFree(p->d_f);
+  if (p->d_ws) hipFree(p->d_ws);
+  if (p->d_part) hipFree(p->d_part);
+}
+
+// Checks shared by exx_apply and the batched form.  Returns KX_OK if valid.
+kx_status check_exx_args(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, const double* occ,
+                         const void* phi, int64_t ld_phi, int n_b, double* vx, int64_t ld_vx,
+                         double* ex, const double* gphi, int path) {
+  if (!p) return fail(KX_EINVAL, "exx_apply: plan is NULL");
+  if (n_occ < 0 || n_b < 0) return fail(KX_EINVAL, "exx_apply: negative n_occ (%d) or n_b (%d)", n_occ, n_b);
+  if (path != KX_PATH_FUSED && path != KX_PATH_PLAIN)
+    return fail(KX_EINVAL, "exx_apply: unknown path %d", path);
+  if (path == KX_PATH_PLAIN && p->prec != KX_PREC_FP64)
+    return fail(KX_EUNSUPPORTED, "exx_apply: the plain path is FP64 only");
+  if (n_occ == 0 || n_b == 0) return KX_OK;
+  if (!psi || !occ || !phi || !vx) return fail(KX_EINVAL, "exx_apply: NULL data pointer");
+  if (ex && !gphi) return fail(KX_EINVAL, "exx_apply: d_ex given without d_gphi");
+  if (ld_psi < p->N || ld_phi < p->N || ld_vx < p->N)
+    return fail(KX_EINVAL, "exx_apply: leading dimension below N = %lld", (long long)p->N);
+  const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+  if (((uintptr_t)psi % eb) || ((uintptr_t)phi % eb) || ((uintptr_t)vx % 8) || ((uintptr_t)occ % 8))
+    return fail(KX_EINVAL, "exx_apply: misaligned pointer");
+  if (p->cplx) return fail(KX_EUNSUPPORTED, "exx_apply: complex (Bloch) plans are not built yet");
+  if (p->prec == KX_PREC_BF16X3 || p->prec == KX_PREC_BF16X6)
+    return fail(KX_EUNSUPPORTED, "exx_apply: split-BF16 precision is not built yet");
+  return KX_OK;
+}
+
+// Enqueue one exx_apply.  Arguments already validated; buffers allocated for
+// the batch size returned by batch_targets().
+int batch_targets(kx_plan p, int n_occ, int n_b) {
+  const size_t per_t = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+  size_t nt = std::max<size_t>(1, workspace_limit() / std::max<size_t>(per_t, 1));
+  return (int)std::min<size_t>(nt, (size_t)n_b);
+}
+
+kx_status prepare_exx(kx_plan p, int n_occ, int n_b, int path) {
+  const int nt = batch_targets(p, n_occ, n_b);
+  const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+  void* ws0 = p->d_ws;
+  void* part0 = p->d_part;
+  kx_status st = ensure_buffer(&p->d_ws, &p->ws_bytes, (size_t)nt * n_occ * p->N * eb, "workspace");
+  if (st != KX_OK) return st;
+  const size_t per_t = std::max<size_t>(64, (size_t)p->n[2]);
+  st = ensure_buffer((void**)&p->d_part, &p->part_bytes, (size_t)nt * per_t * sizeof(double),
+                     "E_x partials");
+  if (p->d_ws != ws0 || p->d_part != part0) ++p->ws_gen;
+  return st;
+}
+
+kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, const double* occ,
+                      const void* phi, int64_t ld_phi, int n_b, double* vx, int64_t ld_vx,
+                      double* ex, const double* gphi, int path, hipStream_t s) {
+  using namespace kx;
+  if (n_occ == 0 || n_b == 0) return KX_OK;
+  // Batch size from the buffers actually held (prepare_exx sized them).
+  const size_t per_t_ws = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+  const size_t per_t_part = std::max<size_t>(64, (size_t)p->n[2]) * sizeof(double);
+  size_t cap = std::min(p->ws_bytes / per_t_ws, p->part_bytes / per_t_part);
+  const int nt = (int)std::min<size_t>(cap, (size_t)n_b);
+  if (nt < 1) return fail(KX_ESTATE, "exx_apply: workspace not prepared");
+  p->last_nt = nt;
+  const size_t eb = elem_bytes(p->prec);
+  const bool f64 = p->prec == KX_PREC_FP64;
+  for (int n0 = 0; n0 < n_b; n0 += nt) {
+    const int cur = std::min(nt, n_b - n0);
+    const int npairs = cur * n_occ;
+    const char* phi0 = (const char*)phi + (size_t)n0 * ld_phi * eb;
+    SliceArgs A{};
+    A.n1 = p->n[0]; A.n2 = p->n[1]; A.n3 = p->n[2]; A.n12 = p->n12; A.N = p->N;
+    A.npairs = npairs; A.n_occ = n_occ;
+    A.psi = psi; A.ld_psi = ld_psi; A.phi = phi0; A.ld_phi = ld_phi;
+    A.src = p->d_ws; A.ld_src = p->N;
+    A.dst = p->d_ws; A.ld_dst = p->N;
+    A.V1 = p->dVmat[0]; A.V2 = p->dVmat[1]; A.P = p->P12;
+    PencilArgs B{};
+    B.n1 = p->n[0]; B.n2 = p->n[1]; B.n3 = p->n[2]; B.n12 = p->n12;
+    B.npairs = npairs; B.nchunks = (p->n12 + 63) / 64;
+    B.T = p->d_ws; B.ld = p->N; B.V3 = p->dVmat[2]; B.P3 = p->P3; B.ftab = p->d_f;
+    AccArgs C{};
+    C.n1 = p->n[0]; C.n2 = p->n[1]; C.n3 = p->n[2]; C.n12 = p->n12; C.N = p->N;
+    C.n_t = cur; C.n_occ = n_occ;
+    C.T = p->d_ws; C.ld_T = p->N;
+    C.psi = psi; C.ld_psi = ld_psi; C.occ = occ;
+    C.phi = phi0; C.ld_phi = ld_phi;
+    C.vx = vx + (size_t)n0 * ld_vx; C.ld_vx = ld_vx;
+    C.partials = ex ? p->d_part : nullptr;
+    C.dst = p->d_ws; C.ld_dst = p->N;
+    C.V1 = p->dVmat[0]; C.V2 = p->dVmat[1]; C.P = p->P12;
+    const int64_t items_pairs = (int64_t)npairs * p->n[2];
+    hipError_t e = hipSuccess;
+    int per_target = p->n[2];
+    if (path == KX_PATH_FUSED) {
+      e = f64 ? launch_slice_fwd_f64(p->nk12, SF_PAIR12, A, items_pairs, p->max_blocks, s)
+              : launch_slice_fwd_f32(p->nk12, SF_PAIR12, A, items_pairs, p->max_blocks, s);
+      if (e == hipSuccess)
+        e = f64 ? launch_pencil_f64(p->nk3, PC_FSI, B, p->max_blocks, s)
+                : launch_pencil_f32(p->nk3, PC_FSI, B, p->max_blocks, s);
+      if (e == hipSuccess)
+        e = f64 ? launch_slice_inv_f64(p->nk12, SI_ACC12, C, (int64_t)cur * p->n[2], p->max_blocks, s)
+                : launch_slice_inv_f32(p->nk12, SI_ACC12, C, (int64_t)cur * p->n[2], p->max_blocks, s);
+    } else {
+      // plain FP64: one kernel per step, each a full pass over the batch
+      e = launch_slice_fwd_f64(p->nk12, SF_PAIR, A, items_pairs, p->max_blocks, s);
+      if (e == hipSuccess) e = launch_slice_fwd_f64(p->nk12, SF_LOAD1, A, items_pairs, p->max_blocks, s);
+      if (e == hipSuccess) e = launch_slice_fwd_f64(p->nk12, SF_LOAD2, A, items_pairs, p->max_blocks, s);
+      if (e == hipSuccess) e = launch_pencil_f64(p->nk3, PC_F, B, p->max_blocks, s);
+      if (e == hipSuccess) e = launch_scale_f64((double*)p->d_ws, p->N, npairs, p->N, p->d_f, s);
+      if (e == hipSuccess) e = launch_pencil_f64(p->nk3, PC_I, B, p->max_blocks, s);
+      AccArgs Cs = C;
+      Cs.n_t = npairs; Cs.n_occ = 1;
+      if (e == hipSuccess) e = launch_slice_inv_f64(p->nk12, SI_ST2, Cs, items_pairs, p->max_blocks, s);
+      if (e == hipSuccess) e = launch_slice_inv_f64(p->nk12, SI_ST1, Cs, items_pairs, p->max_blocks, s);
+      per_target = 64;
+      if (e == hipSuccess) e = launch_accumulate_f64(C, per_target, s);
+    }
+    if (e == hipSuccess && ex) e = launch_ex_finalize(p->d_part, cur, per_target, gphi + n0, p->dV, ex, s);
+    if (e != hipSuccess) return dev_fail(e, "exx_apply launch");
+  }
+  return KX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kx_last_error(void) { return g_err.c_str(); }
+
+kx_status kx_host_fd_weights(int fd_order, double* c) {
+  if (fd_order < 2 || fd_order > 16 || fd_order % 2) return fail(KX_EINVAL, "fd_order must be even in [2, 16]");
+  if (!c) return fail(KX_EINVAL, "NULL output");
+  std::vector<double> w = kx::fd_weights(fd_order);
+  std::copy(w.begin(), w.end(), c);
+  return KX_OK;
+}
+
+kx_status kx_host_eig1d(int n, double h, int bc, int fd_order, double kappa, double* lam,
+                        double* V_re, double* V_im) {
+  if (n < 1 || n > kx::kMaxAxis) return fail(KX_EINVAL, "n must be in [1, %d]", kx::kMaxAxis);
+  if (!(h > 0) || !std::isfinite(h)) return fail(KX_EINVAL, "h must be positive");
+  if (bc != KX_BC_PERIODIC && bc != KX_BC_DIRICHLET) return fail(KX_EINVAL, "unknown bc %d", bc);
+  if (fd_order < 2 || fd_order > 16 || fd_order % 2) return fail(KX_EINVAL, "fd_order must be even in [2, 16]");
+  if (!std::isfinite(kappa) || (kappa != 0.0 && bc != KX_BC_PERIODIC))
+    return fail(KX_EINVAL, "a Bloch wavevector needs a periodic axis");
+  std::vector<double> l, vr, vi;
+  kx::eig1d(n, h, bc, fd_order, kappa, l, vr, vi);
+  if (lam) std::copy(l.begin(), l.end(), lam);
+  if (V_re) std::copy(vr.begin(), vr.end(), V_re);
+  if (V_im) std::copy(vi.begin(), vi.end(), V_im);
+  return KX_OK;
+}
+
+kx_status kron_setup(const int n[3], const double h[3], const int bc[3], int fd_order, double omega,
+                     const double kq[3], int prec, kx_plan* out) {
+  if (!out) return fail(KX_EINVAL, "kron_setup: out is NULL");
+  *out = nullptr;
+  if (!n || !h || !bc) return fail(KX_EINVAL, "kron_setup: NULL n, h or bc");
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 1) return fail(KX_EINVAL, "kron_setup: n[%d] = %d < 1", d, n[d]);
+    if (n[d] > kx::kMaxAxis) return fail(KX_EUNSUPPORTED, "kron_setup: n[%d] = %d > %d", d, n[d], kx::kMaxAxis);
+    if (!(h[d] > 0) || !std::isfinite(h[d])) return fail(KX_EINVAL, "kron_setup: h[%d] must be positive", d);
+    if (bc[d] != KX_BC_PERIODIC && bc[d] != KX_BC_DIRICHLET)
+      return fail(KX_EINVAL, "kron_setup: unknown bc[%d] = %d", d, bc[d]);
+    if (kq && (!std::isfinite(kq[d]) || (kq[d] != 0.0 && bc[d] != KX_BC_PERIODIC)))
+      return fail(KX_EINVAL, "kron_setup: kq[%d] needs a periodic axis", d);
+  }
+  if (fd_order < 2 || fd_order > 16 || fd_order % 2)
+    return fail(KX_EINVAL, "kron_setup: fd_order must be even in [2, 16]");
+  if (!std::isfinite(omega)) return fail(KX_EINVAL, "kron_setup: omega is not finite");
+  if (prec < KX_PREC_FP64 || prec > KX_PREC_BF16X6) return fail(KX_EINVAL, "kron_setup: unknown precision %d", prec);
+  if (prec == KX_PREC_FP64 && std::max(n[0], n[1]) > 128)
+    return fail(KX_EUNSUPPORTED, "kron_setup: FP64 slices are limited to n1, n2 <= 128 (LDS)");
+
+  kx_plan p = new (std::nothrow) kx_plan_s();
+  if (!p) return fail(KX_ENOMEM, "kron_setup: host allocation");
+  for (int d = 0; d < 3; ++d) {
+    p->n[d] = n[d];
+    p->h[d] = h[d];
+    p->bc[d] = bc[d];
+    p->kq[d] = kq ? kq[d] : 0.0;
+  }
+  p->order = fd_order;
+  p->omega = omega;
+  p->prec = prec;
+  p->cplx = p->kq[0] != 0.0 || p->kq[1] != 0.0 || p->kq[2] != 0.0;
+  p->N = (int64_t)n[0] * n[1] * n[2];
+  p->n12 = n[0] * n[1];
+  p->dV = h[0] * h[1] * h[2];
+  for (int d = 0; d < 3; ++d) kx::eig1d(n[d], h[d], bc[d], fd_order, p->kq[d], p->lam[d], p->Vre[d], p->Vim[d]);
+  kx::f_table(p->lam, omega, p->f);
+  p->nk12 = kx::pick_nk(std::max(n[0], n[1]));
+  p->nk3 = kx::pick_nk(n[2]);
+  p->P12 = kx::padded_len(p->nk12);
+  p->P3 = kx::padded_len(p->nk3);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(KX_EDEVICE, "kron_setup: no HIP device");
+  }
+  // Zero-padded eigenvector matrices, V[k*P + a] (k grid index, a mode).
+  const int eb = elem_bytes(prec);
+  for (int d = 0; d < 3; ++d) {
+    const int P = d < 2 ? p->P12 : p->P3;
+    const int nd = n[d];
+    std::vector<char> host((size_t)P * P * eb, 0);
+    for (int k = 0; k < nd; ++k)
+      for (int a = 0; a < nd; ++a) {
+        const double v = p->Vre[d][(size_t)k * nd + a];
+        if (eb == 8)
+          ((double*)host.data())[(size_t)k * P + a] = v;
+        else
+          ((float*)host.data())[(size_t)k * P + a] = (float)v;
+      }
+    hipError_t e = hipMalloc(&p->dVmat[d], host.size());
+    if (e == hipSuccess) e = hipMemcpy(p->dVmat[d], host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_plan_device(p);
+      delete p;
+      return e == hipErrorOutOfMemory ? fail(KX_ENOMEM, "kron_setup: device allocation")
+                                      : dev_fail(e, "kron_setup upload");
+    }
+  }
+  hipError_t e = hipMalloc((void**)&p->d_f, p->f.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(p->d_f, p->f.data(), p->f.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_plan_device(p);
+    delete p;
+    return dev_fail(e, "kron_setup f table");
+  }
+  *out = p;
+  return KX_OK;
+}
+
+kx_status kron_destroy(kx_plan p) {
+  if (!p) return KX_OK;
+  (void)hipDeviceSynchronize();
+  {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+      bool uses = false;
+      for (const kx_task& t : it->tasks) uses |= t.plan == p;
+      if (uses) {
+        hipGraphExecDestroy(it->exec);
+        hipGraphDestroy(it->graph);
+        it = g_graphs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  free_plan_device(p);
+  delete p;
+  return KX_OK;
+}
+
+kx_status kx_plan_info(kx_plan p, int64_t out[8]) {
+  if (!p || !out) return fail(KX_EINVAL, "kx_plan_info: NULL argument");
+  out[0] = p->n[0]; out[1] = p->n[1]; out[2] = p->n[2];
+  out[3] = p->cplx ? 1 : 0;
+  out[4] = p->prec;
+  out[5] = p->P12;
+  out[6] = p->P3;
+  out[7] = p->last_nt;
+  return KX_OK;
+}
+
+kx_status kx_plan_tables(kx_plan p, int axis, double* lam, double* V_re, double* V_im) {
+  if (!p) return fail(KX_EINVAL, "kx_plan_tables: plan is NULL");
+  if (axis < 0 || axis > 3) return fail(KX_EINVAL, "kx_plan_tables: axis must be 0..3");
+  if (axis == 3) {
+    if (lam) std::copy(p->f.begin(), p->f.end(), lam);
+    return KX_OK;
+  }
+  if (lam) std::copy(p->lam[axis].begin(), p->lam[axis].end(), lam);
+  if (V_re) std::copy(p->Vre[axis].begin(), p->Vre[axis].end(), V_re);
+  if (V_im) std::copy(p->Vim[axis].begin(), p->Vim[axis].end(), V_im);
+  return KX_OK;
+}
+
+kx_status kron_solve(kx_plan p, const void* B, int64_t ldb, void* X, int64_t ldx, int nrhs, int path,
+                     void* stream) {
+  using namespace kx;
+  if (!p) return fail(KX_EINVAL, "kron_solve: plan is NULL");
+  if (nrhs < 0) return fail(KX_EINVAL, "kron_solve: nrhs < 0");
+  if (path != KX_PATH_FUSED && path != KX_PATH_PLAIN) return fail(KX_EINVAL, "kron_solve: unknown path");
+  if (path == KX_PATH_PLAIN && p->prec != KX_PREC_FP64)
+    return fail(KX_EUNSUPPORTED, "kron_solve: the plain path is FP64 only");
+  if (nrhs == 0) return KX_OK;
+  if (!B || !X) return fail(KX_EINVAL, "kron_solve: NULL data pointer");
+  if (ldb < p->N || ldx < p->N) return fail(KX_EINVAL, "kron_solve: leading dimension below N");
+  if (p->cplx) return fail(KX_EUNSUPPORTED, "kron_solve: complex (Bloch) plans are not built yet");
+  if (p->prec == KX_PREC_BF16X3 || p->prec == KX_PREC_BF16X6)
+    return fail(KX_EUNSUPPORTED, "kron_solve: split-BF16 precision is not built yet");
+  const size_t eb = elem_bytes(p->prec);
+  {
+    const char* b0 = (const char*)B;
+    const char* b1 = b0 + ((size_t)(nrhs - 1) * ldb + p->N) * eb;
+    const char* x0 = (const char*)X;
+    const char* x1 = x0 + ((size_t)(nrhs - 1) * ldx + p->N) * eb;
+    if (b0 < x1 && x0 < b1) return fail(KX_EINVAL, "kron_solve: B and X overlap");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const bool f64 = p->prec == KX_PREC_FP64;
+  SliceArgs A{};
+  A.n1 = p->n[0]; A.n2 = p->n[1]; A.n3 = p->n[2]; A.n12 = p->n12; A.N = p->N;
+  A.npairs = nrhs; A.n_occ = 1;
+  A.src = B; A.ld_src = ldb; A.dst = X; A.ld_dst = ldx;
+  A.V1 = p->dVmat[0]; A.V2 = p->dVmat[1]; A.P = p->P12;
+  PencilArgs Pn{};
+  Pn.n1 = p->n[0]; Pn.n2 = p->n[1]; Pn.n3 = p->n[2]; Pn.n12 = p->n12;
+  Pn.npairs = nrhs; Pn.nchunks = (p->n12 + 63) / 64;
+  Pn.T = X; Pn.ld = ldx; Pn.V3 = p->dVmat[2]; Pn.P3 = p->P3; Pn.ftab = p->d_f;
+  AccArgs C{};
+  C.n1 = p->n[0]; C.n2 = p->n[1]; C.n3 = p->n[2]; C.n12 = p->n12; C.N = p->N;
+  C.n_t = nrhs; C.n_occ = 1;
+  C.T = X; C.ld_T = ldx; C.dst = X; C.ld_dst = ldx;
+  C.V1 = p->dVmat[0]; C.V2 = p->dVmat[1]; C.P = p->P12;
+  const int64_t items = (int64_t)nrhs * p->n[2];
+  hipError_t e;
+  if (path == KX_PATH_FUSED) {
+    e = f64 ? launch_slice_fwd_f64(p->nk12, SF_LOAD12, A, items, p->max_blocks, s)
+            : launch_slice_fwd_f32(p->nk12, SF_LOAD12, A, items, p->max_blocks, s);
+    if (e == hipSuccess)
+      e = f64 ? launch_pencil_f64(p->nk3, PC_FSI, Pn, p->max_blocks, s)
+              : launch_pencil_f32(p->nk3, PC_FSI, Pn, p->max_blocks, s);
+    if (e == hipSuccess)
+      e = f64 ? launch_slice_inv_f64(p->nk12, SI_ST12, C, items, p->max_blocks, s)
+              : launch_slice_inv_f32(p->nk12, SI_ST12, C, items, p->max_blocks, s);
+  } else {
+    e = launch_slice_fwd_f64(p->nk12, SF_LOAD1, A, items, p->max_blocks, s);
+    A.src = X; A.ld_src = ldx;
+    if (e == hipSuccess) e = launch_slice_fwd_f64(p->nk12, SF_LOAD2, A, items, p->max_blocks, s);
+    if (e == hipSuccess) e = launch_pencil_f64(p->nk3, PC_F, Pn, p->max_blocks, s);
+    if (e == hipSuccess) e = launch_scale_f64((double*)X, ldx, nrhs, p->N, p->d_f, s);
+    if (e == hipSuccess) e = launch_pencil_f64(p->nk3, PC_I, Pn, p->max_blocks, s);
+    if (e == hipSuccess) e = launch_slice_inv_f64(p->nk12, SI_ST2, C, items, p->max_blocks, s);
+    if (e == hipSuccess) e = launch_slice_inv_f64(p->nk12, SI_ST1, C, items, p->max_blocks, s);
+  }
+  if (e != hipSuccess) return dev_fail(e, "kron_solve launch");
+  return KX_OK;
+}
+
+kx_status exx_apply(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, const double* d_occ,
+                    const void* d_phi, int64_t ld_phi, int n_b, double* d_vx, int64_t ld_vx,
+                    double* d_ex, const double* d_gphi, int path, void* stream) {
+  kx_status st = check_exx_args(p, d_psi, ld_psi, n_occ, d_occ, d_phi, ld_phi, n_b, d_vx, ld_vx,
+                                d_ex, d_gphi, path);
+  if (st != KX_OK || n_occ == 0 || n_b == 0) return st;
+  st = prepare_exx(p, n_occ, n_b, path);
+  if (st != KX_OK) return st;
+  return enqueue_exx(p, d_psi, ld_psi, n_occ, d_occ, d_phi, ld_phi, n_b, d_vx, ld_vx, d_ex, d_gphi,
+                     path, (hipStream_t)stream);
+}
+
+kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
+  if (ntasks < 0 || (ntasks > 0 && !tasks)) return fail(KX_EINVAL, "exx_apply_batched: bad task list");
+  if (ntasks == 0) return KX_OK;
+  const int prec0 = tasks[0].plan ? tasks[0].plan->prec : -1;
+  for (int i = 0; i < ntasks; ++i) {
+    const kx_task& t = tasks[i];
+    kx_status st = check_exx_args(t.plan, t.d_psi, t.ld_psi, t.n_occ, t.d_occ, t.d_phi, t.ld_phi,
+                                  t.n_b, t.d_vx, t.ld_vx, t.d_ex, t.d_gphi, KX_PATH_FUSED);
+    if (st != KX_OK) return st;
+    if (t.plan->prec != prec0) return fail(KX_EINVAL, "exx_apply_batched: mixed precisions");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  for (int i = 0; i < ntasks; ++i) {
+    const kx_task& t = tasks[i];
+    if (t.n_occ == 0 || t.n_b == 0) continue;
+    kx_status st = prepare_exx(t.plan, t.n_occ, t.n_b, KX_PATH_FUSED);
+    if (st != KX_OK) return st;
+  }
+  for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
+    kx_graph_entry& g = *it;
+    if (g.stream == s && (int)g.tasks.size() == ntasks &&
+        std::memcmp(g.tasks.data(), tasks, sizeof(kx_task) * ntasks) == 0) {
+      bool fresh = true;
+      for (int i = 0; i < ntasks; ++i) fresh &= g.generations[i] == tasks[i].plan->ws_gen;
+      if (!fresh) {  // a workspace moved since capture: capture again
+        hipGraphExecDestroy(g.exec);
+        hipGraphDestroy(g.graph);
+        g_graphs.erase(it);
+        break;
+      }
+      hipError_t e = hipGraphLaunch(g.exec, s);
+      if (e != hipSuccess) return dev_fail(e, "exx_apply_batched replay");
+      return KX_OK;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return dev_fail(e, "exx_apply_batched capture");
+  kx_status st = KX_OK;
+  for (int i = 0; i < ntasks && st == KX_OK; ++i) {
+    const kx_task& t = tasks[i];
+    st = enqueue_exx(t.plan, t.d_psi, t.ld_psi, t.n_occ, t.d_occ, t.d_phi, t.ld_phi, t.n_b, t.d_vx,
+                     t.ld_vx, t.d_ex, t.d_gphi, KX_PATH_FUSED, s);
+  }
+  e = hipStreamEndCapture(s, &graph);
+  if (st != KX_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return dev_fail(e, "exx_apply_batched end capture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(graph);
+    return dev_fail(e, "exx_apply_batched instantiate");
+  }
+  std::vector<unsigned> gens(ntasks);
+  for (int i = 0; i < ntasks; ++i) gens[i] = tasks[i].plan->ws_gen;
+  g_graphs.push_back(kx_graph_entry{std::vector<kx_task>(tasks, tasks + ntasks), gens, s, graph, exec});
+  e = hipGraphLaunch(exec, s);
+  if (e != hipSuccess) return dev_fail(e, "exx_apply_batched launch");
+  return KX_OK;
+}
+
+}  // extern "C"

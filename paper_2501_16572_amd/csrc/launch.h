@@ -1,0 +1,49 @@
+// Launchers for the templated kernels (one translation unit per element type).
+#pragma once
+
+#include "kernels.h"
+
+namespace kx {
+
+// K-step counts with compiled kernels; an axis of length n uses the smallest
+// NK with 4*NK >= n (the eigenvector matrices are zero-padded).
+static const int kNKList[] = {6, 8, 12, 14, 16, 18, 20, 24, 28, 30, 32, 36, 40};
+static const int kNKCount = sizeof(kNKList) / sizeof(kNKList[0]);
+static const int kMaxAxis = 160;
+
+inline int pick_nk(int n) {
+  for (int i = 0; i < kNKCount; ++i)
+    if (4 * kNKList[i] >= n) return kNKList[i];
+  return -1;
+}
+inline int padded_len(int nk) { return 16 * ((nk + 3) / 4); }
+
+enum SliceFwdVariant { SF_PAIR12 = 0, SF_LOAD12, SF_PAIR, SF_LOAD1, SF_LOAD2 };
+enum PencilVariant { PC_FSI = 0, PC_F, PC_I };
+enum SliceInvVariant { SI_ACC12 = 0, SI_ST12, SI_ST2, SI_ST1 };
+
+// Each launcher picks a persistent grid of at most `max_blocks` blocks
+// (0 = as many as are co-resident on the device) for `items` work items and
+// returns the HIP status of the launch.
+hipError_t launch_slice_fwd_f64(int nk, int variant, const SliceArgs& a, int64_t items,
+                                int max_blocks, hipStream_t s);
+hipError_t launch_pencil_f64(int nk, int variant, const PencilArgs& a, int max_blocks,
+                             hipStream_t s);
+hipError_t launch_slice_inv_f64(int nk, int variant, const AccArgs& a, int64_t items,
+                                int max_blocks, hipStream_t s);
+hipError_t launch_slice_fwd_f32(int nk, int variant, const SliceArgs& a, int64_t items,
+                                int max_blocks, hipStream_t s);
+hipError_t launch_pencil_f32(int nk, int variant, const PencilArgs& a, int max_blocks,
+                             hipStream_t s);
+hipError_t launch_slice_inv_f32(int nk, int variant, const AccArgs& a, int64_t items,
+                                int max_blocks, hipStream_t s);
+hipError_t launch_scale_f64(double* T, int64_t ld, int npairs, int64_t N, const double* ftab,
+                            hipStream_t s);
+hipError_t launch_accumulate_f64(const AccArgs& a, int blocks_per_target, hipStream_t s);
+hipError_t launch_ex_finalize(const double* partials, int n_t, int per_target,
+                              const double* gphi, double dV, double* ex, hipStream_t s);
+
+// Number of compute units of the current device (cached).
+int device_cu_count();
+
+}  // namespace kx

@@ -1,0 +1,236 @@
+"""Thin Python binding of ``libkronx.so`` (argument marshalling only).
+
+Every step of the exact-exchange path runs in the library's HIP kernels; this
+module converts torch tensors to pointers, leading dimensions and the current
+HIP stream, and raises on a non-OK status.  It raises ImportError-like
+``RuntimeError`` when the library has not been built: there is no fallback.
+
+Tensor conventions: a set of grid functions is a 2D tensor of shape
+(ncols, N) with unit stride along N (one grid function per row, i.e. the
+column-major N x ncols matrix of the C interface); the leading dimension is
+the row stride.  Real plans take float64 (FP64) or float32 (other precisions);
+complex plans take complex128 / complex64.  Vx outputs are float64 /
+complex128.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkronx.so")
+
+KX_OK, KX_EINVAL, KX_EUNSUPPORTED, KX_ENOMEM, KX_EDEVICE, KX_ESTATE = range(6)
+STATUS_NAMES = {0: "KX_OK", 1: "KX_EINVAL", 2: "KX_EUNSUPPORTED", 3: "KX_ENOMEM",
+                4: "KX_EDEVICE", 5: "KX_ESTATE"}
+BC = {"periodic": 0, "dirichlet": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+PATH = {"fused": 0, "plain": 1}
+
+# Every symbol declared in include/kronx.h.
+EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_batched",
+           "kx_plan_info", "kx_plan_tables", "kx_host_eig1d", "kx_host_fd_weights",
+           "kx_last_error"]
+
+
+class KronxError(RuntimeError):
+    def __init__(self, status, where, text):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {text}")
+        self.status = status
+
+
+class _Task(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("d_psi", ctypes.c_void_p), ("ld_psi", ctypes.c_int64),
+                ("n_occ", ctypes.c_int), ("d_occ", ctypes.c_void_p), ("d_phi", ctypes.c_void_p),
+                ("ld_phi", ctypes.c_int64), ("n_b", ctypes.c_int), ("d_vx", ctypes.c_void_p),
+                ("ld_vx", ctypes.c_int64), ("d_ex", ctypes.c_void_p), ("d_gphi", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libkronx.so once; raise if it is missing (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"libkronx.so not built at {path}: run __graft_entry__.build() "
+                           "or python -m paper_2501_16572_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i64, ci, cd = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    ip = ctypes.POINTER(ctypes.c_int)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.kron_setup.argtypes = [ip, dp, ip, ci, cd, dp, ci, ctypes.POINTER(vp)]
+    lib.kron_destroy.argtypes = [vp]
+    lib.kron_solve.argtypes = [vp, vp, i64, vp, i64, ci, ci, vp]
+    lib.exx_apply.argtypes = [vp, vp, i64, ci, vp, vp, i64, ci, vp, i64, vp, vp, ci, vp]
+    lib.exx_apply_batched.argtypes = [ctypes.POINTER(_Task), ci, vp]
+    lib.kx_plan_info.argtypes = [vp, i64p]
+    lib.kx_plan_tables.argtypes = [vp, ci, dp, dp, dp]
+    lib.kx_host_eig1d.argtypes = [ci, cd, ci, ci, cd, dp, dp, dp]
+    lib.kx_host_fd_weights.argtypes = [ci, dp]
+    lib.kx_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "kx_last_error":
+            getattr(lib, name).restype = ci
+    _lib = lib
+    return lib
+
+
+def kx_last_error():
+    return load_library().kx_last_error().decode()
+
+
+def _check(status, where):
+    if status != KX_OK:
+        raise KronxError(status, where, kx_last_error())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Handle of a kx_plan (kron_setup's output)."""
+
+    def __init__(self, handle, n, h, bc, order, omega, kq, prec):
+        self.handle = handle
+        self.n, self.h, self.bc = tuple(n), tuple(h), tuple(bc)
+        self.order, self.omega, self.kq, self.prec = order, omega, tuple(kq), prec
+        self.complex = any(k != 0.0 for k in self.kq)
+        self.N = int(np.prod(self.n))
+        self.dV = float(np.prod(self.h))
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float64 if self.prec == "fp64" else torch.float32
+
+    @property
+    def dtype(self):
+        import torch
+        if self.complex:
+            return torch.complex128 if self.prec == "fp64" else torch.complex64
+        return self.real_dtype
+
+    def info(self):
+        out = (ctypes.c_int64 * 8)()
+        _check(load_library().kx_plan_info(self.handle, out), "kx_plan_info")
+        return list(out)
+
+    def tables(self, axis):
+        """Host FP64 tables: (lam, V) for axis 0..2 (V[k, a]), or the f table for axis 3."""
+        lib = load_library()
+        if axis == 3:
+            f = np.empty(self.N)
+            _check(lib.kx_plan_tables(self.handle, 3, _dptr(f), None, None), "kx_plan_tables")
+            return f
+        nd = self.n[axis]
+        lam = np.empty(nd)
+        vr = np.empty((nd, nd))
+        vi = np.empty((nd, nd))
+        _check(lib.kx_plan_tables(self.handle, axis, _dptr(lam), _dptr(vr), _dptr(vi)),
+               "kx_plan_tables")
+        return lam, (vr + 1j * vi if self.complex else vr)
+
+    def destroy(self):
+        if self.handle:
+            _check(load_library().kron_destroy(self.handle), "kron_destroy")
+            self.handle = None
+
+
+def kron_setup(n, h, bc=("periodic",) * 3, fd_order=12, omega=0.0, kq=None, prec="fp64"):
+    lib = load_library()
+    bcs = [BC[b] if isinstance(b, str) else int(b) for b in bc]
+    kqv = (ctypes.c_double * 3)(*kq) if kq is not None else None
+    handle = ctypes.c_void_p()
+    st = lib.kron_setup((ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*h), (ctypes.c_int * 3)(*bcs),
+                        int(fd_order), float(omega), kqv, PREC[prec], ctypes.byref(handle))
+    _check(st, "kron_setup")
+    return Plan(handle, n, h, bc, fd_order, omega, kq if kq is not None else (0.0, 0.0, 0.0), prec)
+
+
+def kron_destroy(plan):
+    plan.destroy()
+
+
+def _cols(t, N, what):
+    if t.dim() != 2 or t.stride(1) != 1 or t.shape[1] < N:
+        raise ValueError(f"{what}: expected a (ncols, >=N) tensor with unit stride along the grid")
+    return t.data_ptr(), t.stride(0)
+
+
+def kron_solve(plan, B, X=None, path="fused", stream=None):
+    """X = f(L) B for the rows of B (shape (nrhs, N)); returns X."""
+    import torch
+    if X is None:
+        X = torch.empty_like(B)
+    pb, ldb = _cols(B, plan.N, "B")
+    px, ldx = _cols(X, plan.N, "X")
+    st = load_library().kron_solve(plan.handle, ctypes.c_void_p(pb), ldb, ctypes.c_void_p(px), ldx,
+                                   B.shape[0], PATH[path], _stream(stream))
+    _check(st, "kron_solve")
+    return X
+
+
+def exx_apply(plan, psi, occ, phi, vx, ex=None, gphi=None, path="fused", stream=None):
+    """vx[n] += -sum_m occ[m] psi[m] * f(L)(conj(psi[m]) * phi[n]); ex += dV sum_n gphi[n] <phi_n, dvx_n>.
+
+    psi: (n_occ, N), occ: (n_occ,) float64, phi: (n_b, N), vx: (n_b, N) float64
+    (complex128 for complex plans), ex: (1,) float64 or None, gphi: (n_b,) float64.
+    All CUDA tensors.  Returns vx.
+    """
+    pp, ldp = _cols(psi, plan.N, "psi")
+    pf, ldf = _cols(phi, plan.N, "phi")
+    pv, ldv = _cols(vx, plan.N, "vx")
+    st = load_library().exx_apply(
+        plan.handle, ctypes.c_void_p(pp), ldp, psi.shape[0], ctypes.c_void_p(occ.data_ptr()),
+        ctypes.c_void_p(pf), ldf, phi.shape[0], ctypes.c_void_p(pv), ldv,
+        ctypes.c_void_p(ex.data_ptr()) if ex is not None else None,
+        ctypes.c_void_p(gphi.data_ptr()) if gphi is not None else None,
+        PATH[path], _stream(stream))
+    _check(st, "exx_apply")
+    return vx
+
+
+def exx_apply_batched(tasks, stream=None):
+    """tasks: list of dicts with keys plan, psi, occ, phi, vx, ex (opt), gphi (opt)."""
+    arr = (_Task * len(tasks))()
+    for i, t in enumerate(tasks):
+        plan = t["plan"]
+        pp, ldp = _cols(t["psi"], plan.N, "psi")
+        pf, ldf = _cols(t["phi"], plan.N, "phi")
+        pv, ldv = _cols(t["vx"], plan.N, "vx")
+        ex, gphi = t.get("ex"), t.get("gphi")
+        arr[i] = _Task(plan.handle.value, pp, ldp, t["psi"].shape[0], t["occ"].data_ptr(), pf, ldf,
+                       t["phi"].shape[0], pv, ldv, ex.data_ptr() if ex is not None else None,
+                       gphi.data_ptr() if gphi is not None else None)
+    _check(load_library().exx_apply_batched(arr, len(tasks), _stream(stream)), "exx_apply_batched")
+
+
+def kx_host_eig1d(n, h, bc, fd_order=12, kappa=0.0):
+    """Host-only: (lam, V) of the 1D operator as the plan computes them, V[k, a]."""
+    lam = np.empty(n)
+    vr = np.empty((n, n))
+    vi = np.empty((n, n))
+    st = load_library().kx_host_eig1d(n, h, BC[bc] if isinstance(bc, str) else bc, fd_order,
+                                      kappa, _dptr(lam), _dptr(vr), _dptr(vi))
+    _check(st, "kx_host_eig1d")
+    return lam, (vr + 1j * vi if kappa != 0.0 else vr)
+
+
+def kx_host_fd_weights(fd_order):
+    c = np.empty(fd_order // 2 + 1)
+    _check(load_library().kx_host_fd_weights(fd_order, _dptr(c)), "kx_host_fd_weights")
+    return c

@@ -1,0 +1,99 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load and export every function include/kronx.h declares;
+the host plan's FD weights and 1D eigenpairs must match the oracle (compared
+through basis-invariant quantities: eigenvalues and V diag(lam) V^H, never
+eigenvectors entrywise); argument errors must come back as status codes
+before any device work.
+"""
+
+import ctypes
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle.fd import fd_weights, second_derivative_1d
+from paper_2501_16572_amd import kronx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "kronx.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"(?:kx_status|const char\s*\*)\s*(\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = kronx.load_library()
+    declared = _declared_functions()
+    assert set(declared) == set(kronx.EXPORTS), declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("order", [2, 4, 8, 12, 16])
+def test_host_fd_weights_match_oracle(order):
+    c = kronx.kx_host_fd_weights(order)
+    ref = [float(x) for x in fd_weights(order)]
+    assert np.allclose(c, ref, rtol=1e-15, atol=1e-15)
+
+
+CASES = [(24, 0.3, "periodic", 0.0), (25, 0.25, "periodic", 0.0), (7, 0.4, "periodic", 0.0),
+         (72, 0.25, "periodic", 0.0), (16, 0.3, "periodic", 0.37), (9, 0.3, "periodic", -1.2),
+         (30, 0.3125, "dirichlet", 0.0), (11, 0.2, "dirichlet", 0.0), (5, 0.3, "periodic", 0.0)]
+
+
+@pytest.mark.parametrize("n,h,bc,kappa", CASES)
+def test_host_eig1d_reconstructs_oracle_operator(n, h, bc, kappa):
+    lam, V = kronx.kx_host_eig1d(n, h, bc, 12, kappa)
+    D = second_derivative_1d(n, h, bc, 12, kappa)
+    scale = np.abs(lam).max()
+    # ascending, matches the oracle operator's spectrum
+    assert np.all(np.diff(lam) >= -1e-12 * scale)
+    ref = np.linalg.eigvalsh(D)
+    assert np.allclose(lam, ref, rtol=0, atol=1e-11 * scale)
+    # orthonormal (unitary) and V diag(lam) V^H == D
+    assert np.allclose(V.conj().T @ V, np.eye(n), atol=1e-13)
+    assert np.allclose((V * lam) @ V.conj().T, D, atol=1e-11 * scale)
+    if kappa == 0.0:
+        assert not np.iscomplexobj(V)
+
+
+def test_host_eig1d_zero_mode_exact():
+    lam, _ = kronx.kx_host_eig1d(24, 0.3, "periodic", 12, 0.0)
+    assert lam[-1] == 0.0  # periodic: the constant mode is exactly zero
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=(0, 8, 8)), dict(n=(8, 8, 200)), dict(h=(0.3, -0.1, 0.3)), dict(bc=(0, 5, 0)),
+    dict(fd_order=7), dict(fd_order=0), dict(kq=(0.0, 0.0, 0.3), bc=(0, 0, 1)),
+    dict(prec="bogus"),
+])
+def test_kron_setup_argument_errors(bad):
+    args = dict(n=(8, 8, 8), h=(0.3, 0.3, 0.3), bc=(0, 0, 0), fd_order=12, omega=0.0, kq=None,
+                prec="fp64")
+    args.update(bad)
+    lib = kronx.load_library()
+    handle = ctypes.c_void_p(1234)
+    prec = kronx.PREC.get(args["prec"], 99)
+    kq = (ctypes.c_double * 3)(*args["kq"]) if args["kq"] else None
+    st = lib.kron_setup((ctypes.c_int * 3)(*args["n"]), (ctypes.c_double * 3)(*args["h"]),
+                        (ctypes.c_int * 3)(*args["bc"]), args["fd_order"], args["omega"], kq,
+                        prec, ctypes.byref(handle))
+    assert st in (kronx.KX_EINVAL, kronx.KX_EUNSUPPORTED)
+    assert handle.value is None
+    assert kronx.kx_last_error() != ""
+
+
+def test_null_plan_errors():
+    lib = kronx.load_library()
+    assert lib.kron_solve(None, None, 0, None, 0, 1, 0, None) == kronx.KX_EINVAL
+    assert lib.exx_apply(None, None, 0, 1, None, None, 0, 1, None, 0, None, None, 0, None) == kronx.KX_EINVAL
+    assert lib.kron_destroy(None) == kronx.KX_OK
+    assert lib.exx_apply_batched(None, -1, None) == kronx.KX_EINVAL
+    assert lib.kx_host_eig1d(0, 0.3, 0, 12, 0.0, None, None, None) == kronx.KX_EINVAL
+    assert lib.kx_host_fd_weights(5, None) == kronx.KX_EINVAL
