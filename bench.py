@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of exx_apply (Vx.psi through the batched Kronecker Poisson solver).
+
+Workload (default ``hse72``): Gamma point, 72^3 periodic grid, h = 0.25 bohr,
+12th-order FD Laplacian, 128 orbitals of which 96 are occupied with Fermi
+occupations (kT = 0.01 Ha), screened erfc(omega r)/r kernel with
+omega = 0.106 bohr^-1; one step = one exx_apply over all 128 x 96 pair solves
+(plus E_x), inputs resident in device memory.  Synthetic seeded orbitals
+(smooth random Fourier coefficients, QR-orthonormalized) stand in for the
+paper's DFT orbitals.
+
+Prints ONE JSON line on stdout.  ``value`` is pair Poisson solves per second of
+the FP64 fused path; the same line reports the plain FP64 path and the FP32
+mixed path on the same inputs with their errors, the roofline of the dominant
+kernel from HIP events recorded around every kernel launch in the timed region,
+and the oracle timed on the host on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6}
+METRIC = "Poisson solves/s + MFMA TFLOP/s in exx_apply, mixed vs FP64, at stated err"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pass_flops(n, npairs):
+    """Algorithmic flops per pass for npairs real solves: pass A and C do the
+    mode-1 and mode-2 products (2 N n_d each), pass B both mode-3 products."""
+    n1, n2, n3 = n
+    N = n1 * n2 * n3
+    return {"exx_fused_passA": 2.0 * N * (n1 + n2) * npairs,
+            "exx_fused_passB": 4.0 * N * n3 * npairs,
+            "exx_fused_passC": 2.0 * N * (n1 + n2) * npairs}
+
+
+def run_form(kx, torch, cfg, psi_d, g_d, prec, path, steps, warmup, n_occ):
+    """Time `steps` exx_apply calls; returns timing, per-kernel trace and the
+    result of one clean call."""
+    plan = kx.kron_setup(cfg["n"], cfg["h"], cfg["bc"], cfg["order"], cfg["omega"], prec=prec)
+    try:
+        dt = plan.real_dtype
+        psi = psi_d.to(dt)
+        occ = g_d[:n_occ].contiguous()
+        vx = torch.zeros(psi.shape, dtype=torch.float64, device="cuda")
+        ex = torch.zeros(1, dtype=torch.float64, device="cuda")
+        kx.exx_apply(plan, psi[:n_occ], occ, psi, vx, ex=ex, gphi=g_d, path=path)
+        torch.cuda.synchronize()
+        result = (vx.clone(), float(ex.item()))
+        for _ in range(warmup):
+            kx.exx_apply(plan, psi[:n_occ], occ, psi, vx, ex=ex, gphi=g_d, path=path)
+        torch.cuda.synchronize()
+        kx.kx_trace_enable(True)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            kx.exx_apply(plan, psi[:n_occ], occ, psi, vx, ex=ex, gphi=g_d, path=path)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = e0.elapsed_time(e1)
+        trace = kx.kx_trace_read()
+        kx.kx_trace_enable(False)
+        nt = plan.info()[7]
+    finally:
+        plan.destroy()
+    return dict(ms=ms, wall=wall, trace=trace, result=result, batch_targets=nt)
+
+
+def cpu_baseline(cfg, psi, g, n_occ, bands):
+    """The oracle as it stands, single BLAS thread, on `bands` target bands."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.exx import vx_apply
+    from oracle.kron import KronSolver
+    S = KronSolver(cfg["n"], cfg["h"], cfg["bc"], cfg["order"], cfg["omega"])
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        W = vx_apply(psi[:n_occ], g[:n_occ], psi[:bands], S)
+        dt = time.perf_counter() - t0
+    return W, dict(value=bands * n_occ / dt, unit="solves/s", cores=1, kind="oracle",
+                   sample=f"{bands} target bands x {n_occ} occupied = {bands * n_occ} pair solves "
+                          f"of the same workload, FP64 NumPy, 1 thread, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="hse72")
+    ap.add_argument("--forms", default="fp64:fused,fp64:plain,fp32:fused",
+                    help="comma list of prec:path; the first one gives `value`")
+    ap.add_argument("--cpu-bands", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the exchange path of this library is a "
+              "single-device build (see the sharding notes in DESIGN.md); use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2501_16572_amd import kronx as kx
+    from paper_2501_16572_amd.workloads import CONFIGS, make_inputs
+
+    kx.load_library()
+    cfg = CONFIGS[args.workload]
+    n_occ = cfg["n_occ"]
+    n1, n2, n3 = cfg["n"]
+    N = n1 * n2 * n3
+    log("generating inputs", args.workload)
+    psi, g = make_inputs(cfg)
+    n_b = psi.shape[0]
+    psi_d = torch.from_numpy(psi).cuda()
+    g_d = torch.from_numpy(g).cuda()
+    solves = n_b * n_occ
+    flops_per_solve = 4.0 * N * (n1 + n2 + n3)
+
+    forms = [f.split(":") for f in args.forms.split(",") if f]
+    out_forms = {}
+    ref_vx, ref_ex = None, None
+    head = None
+    for prec, path in forms:
+        log("timing", prec, path)
+        r = run_form(kx, torch, cfg, psi_d, g_d, prec, path, args.steps, args.warmup, n_occ)
+        t = r["ms"] / 1e3
+        sps = solves * args.steps / t
+        form = dict(solves_per_s=sps, ms_per_step=r["ms"] / args.steps,
+                    useful_tflops=flops_per_solve * solves * args.steps / t / 1e12,
+                    batch_targets=r["batch_targets"],
+                    kernels_ms={k: round(v[0] / args.steps, 4) for k, v in r["trace"].items()})
+        vx, ex = r["result"]
+        if ref_vx is None:
+            ref_vx, ref_ex = vx, ex
+        else:
+            d = (vx - ref_vx).norm() / ref_vx.norm()
+            form["rel_err_vs_fp64_device"] = float(d)
+            atoms = 2.0 * float(g.sum()) / 14.0
+            form["ex_err_per_atom_vs_fp64_device"] = abs(ex - ref_ex) / atoms
+        out_forms[f"{prec}_{path}"] = form
+        if head is None:
+            head = (prec, path, r, t)
+        del vx
+        torch.cuda.empty_cache()
+
+    prec, path, r, t = head
+    # roofline of the dominant kernel of the headline form (fused passes)
+    flops = pass_flops(cfg["n"], solves * args.steps)
+    kern = {k: v for k, v in r["trace"].items() if k in flops}
+    roof = None
+    if kern:
+        dom = max(kern, key=lambda k: kern[k][0])
+        ms_tot, launches = kern[dom]
+        achieved = flops[dom] / (ms_tot / 1e3) / 1e12
+        roof = dict(bound="mfma", kernel=dom, achieved=achieved, peak=PEAK_TFLOPS[prec],
+                    unit="TFLOP/s", frac=achieved / PEAK_TFLOPS[prec], traffic=None,
+                    avg_launch_ms=ms_tot / launches, launches=launches)
+
+    # accuracy of the headline result on sampled bands against the oracle
+    cpu = None
+    sample_err = None
+    if not args.no_cpu:
+        log("oracle sample on the host")
+        W, cpu = cpu_baseline(cfg, psi, g, n_occ, args.cpu_bands)
+        dev = ref_vx[:args.cpu_bands].cpu().numpy()
+        sample_err = float(np.linalg.norm(dev - W) / np.linalg.norm(W))
+
+    line = {
+        "metric": METRIC,
+        "value": round(solves * args.steps / t, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(cfg["n"]), "h_bohr": cfg["h"][0],
+                   "fd_order": cfg["order"], "kernel": f"erfc omega={cfg['omega']}" if cfg["omega"] > 0 else "coulomb",
+                   "n_bands": n_b, "n_occ": n_occ, "pair_solves_per_step": solves,
+                   "form": f"{prec}:{path}"},
+        "useful_tflops": round(flops_per_solve * solves * args.steps / t / 1e12, 3),
+        "ex_hartree": ref_ex,
+        "rel_err_sampled_vs_oracle": sample_err,
+        "forms": out_forms,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

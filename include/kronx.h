@@ -189,6 +189,24 @@ kx_status kx_host_eig1d(int n, double h, int bc, int fd_order, double kappa, dou
  * the central second-derivative stencil, f'' ~ sum_s c_|s| f(x + s h) / h^2. */
 kx_status kx_host_fd_weights(int fd_order, double* c);
 
+/* Kernel-level tracing.  While enabled, every kernel the library enqueues
+ * outside graph capture is bracketed by two HIP events recorded on its launch
+ * stream; kx_trace_read waits for those events and folds the elapsed times
+ * into per-kind totals.  Kinds (kx_trace_name gives the text):
+ *   0..3   fused exx_apply: pass A, pass B, pass C, E_x finalize
+ *   4..12  plain exx_apply: pair density, mode-1/2/3 forward, scaling,
+ *          mode-3/2/1 inverse, accumulation
+ *   13..15 fused kron_solve: forward slices, pencils, inverse slices
+ *   16..21 plain kron_solve: mode-1/2/3 forward, scaling, mode-3/2 inverse
+ *   22     plain kron_solve: mode-1 inverse
+ * kx_trace_enable(1) clears the totals; kx_trace_enable(0) stops recording.
+ * kx_trace_read copies min(nkinds, KX_TRACE_KINDS) totals: ms[k] summed
+ * milliseconds, count[k] launches (either pointer may be NULL). */
+#define KX_TRACE_KINDS 23
+kx_status kx_trace_enable(int on);
+kx_status kx_trace_read(double* ms, int64_t* count, int nkinds);
+const char* kx_trace_name(int kind);
+
 /* kx_last_error -- text for this thread's last non-OK status ("" if none).
  * The pointer stays valid until the next call on this thread. */
 const char* kx_last_error(void);

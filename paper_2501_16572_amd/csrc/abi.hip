@@ -90,6 +90,64 @@ hipError_t launch_ex_finalize(const double* partials, int n_t, int per_target, c
 
 }  // namespace kx
 
+// ---------------------------------------------------------------------------
+// Kernel tracing (HIP events around each launch, outside graph capture).
+// ---------------------------------------------------------------------------
+namespace {
+
+enum TraceKind {
+  TK_A = 0, TK_B, TK_C, TK_FIN,
+  TK_P_PAIR, TK_P_M1F, TK_P_M2F, TK_P_M3F, TK_P_SCALE, TK_P_M3I, TK_P_M2I, TK_P_M1I, TK_P_ACC,
+  TK_S_A, TK_S_B, TK_S_C,
+  TK_SP_M1F, TK_SP_M2F, TK_SP_M3F, TK_SP_SCALE, TK_SP_M3I, TK_SP_M2I, TK_SP_M1I,
+  TK_COUNT
+};
+static_assert(TK_COUNT == KX_TRACE_KINDS, "trace kinds");
+const char* const kTraceNames[TK_COUNT] = {
+    "exx_fused_passA", "exx_fused_passB", "exx_fused_passC", "exx_ex_finalize",
+    "exx_plain_pair_density", "exx_plain_mode1_fwd", "exx_plain_mode2_fwd", "exx_plain_mode3_fwd",
+    "exx_plain_scale", "exx_plain_mode3_inv", "exx_plain_mode2_inv", "exx_plain_mode1_inv",
+    "exx_plain_accumulate",
+    "solve_fused_passA", "solve_fused_passB", "solve_fused_passC",
+    "solve_plain_mode1_fwd", "solve_plain_mode2_fwd", "solve_plain_mode3_fwd", "solve_plain_scale",
+    "solve_plain_mode3_inv", "solve_plain_mode2_inv", "solve_plain_mode1_inv"};
+
+struct TraceRec {
+  int kind;
+  hipEvent_t a, b;
+};
+std::mutex g_tr_mu;
+bool g_trace_on = false;
+std::vector<TraceRec> g_tr_pending;
+double g_tr_ms[TK_COUNT];
+int64_t g_tr_n[TK_COUNT];
+
+// Launch `fn` (returning hipError_t) on stream s, bracketed by events when
+// tracing is on and s is not being captured.
+template <typename F>
+hipError_t traced(int kind, hipStream_t s, F fn) {
+  bool on;
+  {
+    std::lock_guard<std::mutex> lock(g_tr_mu);
+    on = g_trace_on;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (on && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+    TraceRec r{kind, nullptr, nullptr};
+    if (hipEventCreate(&r.a) == hipSuccess && hipEventCreate(&r.b) == hipSuccess) {
+      hipEventRecord(r.a, s);
+      hipError_t e = fn();
+      hipEventRecord(r.b, s);
+      std::lock_guard<std::mutex> lock(g_tr_mu);
+      g_tr_pending.push_back(r);
+      return e;
+    }
+  }
+  return fn();
+}
+
+}  // namespace
+
 struct kx_graph_entry {
   std::vector<kx_task> tasks;
   std::vector<unsigned> generations;  // workspace generation of each task's plan at capture
@@ -258,30 +316,44 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
     hipError_t e = hipSuccess;
     int per_target = p->n[2];
     if (path == KX_PATH_FUSED) {
-      e = f64 ? launch_slice_fwd_f64(p->nk12, SF_PAIR12, A, items_pairs, p->max_blocks, s)
-              : launch_slice_fwd_f32(p->nk12, SF_PAIR12, A, items_pairs, p->max_blocks, s);
+      e = traced(TK_A, s, [&] {
+        return f64 ? launch_slice_fwd_f64(p->nk12, SF_PAIR12, A, items_pairs, p->max_blocks, s)
+                   : launch_slice_fwd_f32(p->nk12, SF_PAIR12, A, items_pairs, p->max_blocks, s);
+      });
       if (e == hipSuccess)
-        e = f64 ? launch_pencil_f64(p->nk3, PC_FSI, B, p->max_blocks, s)
-                : launch_pencil_f32(p->nk3, PC_FSI, B, p->max_blocks, s);
+        e = traced(TK_B, s, [&] {
+          return f64 ? launch_pencil_f64(p->nk3, PC_FSI, B, p->max_blocks, s)
+                     : launch_pencil_f32(p->nk3, PC_FSI, B, p->max_blocks, s);
+        });
       if (e == hipSuccess)
-        e = f64 ? launch_slice_inv_f64(p->nk12, SI_ACC12, C, (int64_t)cur * p->n[2], p->max_blocks, s)
-                : launch_slice_inv_f32(p->nk12, SI_ACC12, C, (int64_t)cur * p->n[2], p->max_blocks, s);
+        e = traced(TK_C, s, [&] {
+          const int64_t it = (int64_t)cur * p->n[2];
+          return f64 ? launch_slice_inv_f64(p->nk12, SI_ACC12, C, it, p->max_blocks, s)
+                     : launch_slice_inv_f32(p->nk12, SI_ACC12, C, it, p->max_blocks, s);
+        });
     } else {
       // plain FP64: one kernel per step, each a full pass over the batch
-      e = launch_slice_fwd_f64(p->nk12, SF_PAIR, A, items_pairs, p->max_blocks, s);
-      if (e == hipSuccess) e = launch_slice_fwd_f64(p->nk12, SF_LOAD1, A, items_pairs, p->max_blocks, s);
-      if (e == hipSuccess) e = launch_slice_fwd_f64(p->nk12, SF_LOAD2, A, items_pairs, p->max_blocks, s);
-      if (e == hipSuccess) e = launch_pencil_f64(p->nk3, PC_F, B, p->max_blocks, s);
-      if (e == hipSuccess) e = launch_scale_f64((double*)p->d_ws, p->N, npairs, p->N, p->d_f, s);
-      if (e == hipSuccess) e = launch_pencil_f64(p->nk3, PC_I, B, p->max_blocks, s);
+      const int mb = p->max_blocks;
+      e = traced(TK_P_PAIR, s, [&] { return launch_slice_fwd_f64(p->nk12, SF_PAIR, A, items_pairs, mb, s); });
+      if (e == hipSuccess)
+        e = traced(TK_P_M1F, s, [&] { return launch_slice_fwd_f64(p->nk12, SF_LOAD1, A, items_pairs, mb, s); });
+      if (e == hipSuccess)
+        e = traced(TK_P_M2F, s, [&] { return launch_slice_fwd_f64(p->nk12, SF_LOAD2, A, items_pairs, mb, s); });
+      if (e == hipSuccess) e = traced(TK_P_M3F, s, [&] { return launch_pencil_f64(p->nk3, PC_F, B, mb, s); });
+      if (e == hipSuccess)
+        e = traced(TK_P_SCALE, s, [&] { return launch_scale_f64((double*)p->d_ws, p->N, npairs, p->N, p->d_f, s); });
+      if (e == hipSuccess) e = traced(TK_P_M3I, s, [&] { return launch_pencil_f64(p->nk3, PC_I, B, mb, s); });
       AccArgs Cs = C;
       Cs.n_t = npairs; Cs.n_occ = 1;
-      if (e == hipSuccess) e = launch_slice_inv_f64(p->nk12, SI_ST2, Cs, items_pairs, p->max_blocks, s);
-      if (e == hipSuccess) e = launch_slice_inv_f64(p->nk12, SI_ST1, Cs, items_pairs, p->max_blocks, s);
+      if (e == hipSuccess)
+        e = traced(TK_P_M2I, s, [&] { return launch_slice_inv_f64(p->nk12, SI_ST2, Cs, items_pairs, mb, s); });
+      if (e == hipSuccess)
+        e = traced(TK_P_M1I, s, [&] { return launch_slice_inv_f64(p->nk12, SI_ST1, Cs, items_pairs, mb, s); });
       per_target = 64;
-      if (e == hipSuccess) e = launch_accumulate_f64(C, per_target, s);
+      if (e == hipSuccess) e = traced(TK_P_ACC, s, [&] { return launch_accumulate_f64(C, per_target, s); });
     }
-    if (e == hipSuccess && ex) e = launch_ex_finalize(p->d_part, cur, per_target, gphi + n0, p->dV, ex, s);
+    if (e == hipSuccess && ex)
+      e = traced(TK_FIN, s, [&] { return launch_ex_finalize(p->d_part, cur, per_target, gphi + n0, p->dV, ex, s); });
     if (e != hipSuccess) return dev_fail(e, "exx_apply launch");
   }
   return KX_OK;
@@ -292,6 +364,65 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
 extern "C" {
 
 const char* kx_last_error(void) { return g_err.c_str(); }
+
+kx_status kx_trace_enable(int on) {
+  std::vector<TraceRec> drop;
+  {
+    std::lock_guard<std::mutex> lock(g_tr_mu);
+    g_trace_on = on != 0;
+    if (on) {
+      drop.swap(g_tr_pending);
+      for (int k = 0; k < TK_COUNT; ++k) {
+        g_tr_ms[k] = 0.0;
+        g_tr_n[k] = 0;
+      }
+    }
+  }
+  for (TraceRec& r : drop) {
+    hipEventSynchronize(r.b);
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  return KX_OK;
+}
+
+kx_status kx_trace_read(double* ms, int64_t* count, int nkinds) {
+  if (nkinds < 0) return fail(KX_EINVAL, "kx_trace_read: nkinds < 0");
+  std::vector<TraceRec> recs;
+  {
+    std::lock_guard<std::mutex> lock(g_tr_mu);
+    recs.swap(g_tr_pending);
+  }
+  kx_status st = KX_OK;
+  std::vector<double> add(TK_COUNT, 0.0);
+  std::vector<int64_t> addn(TK_COUNT, 0);
+  for (TraceRec& r : recs) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess && st == KX_OK) st = dev_fail(e, "kx_trace_read");
+    add[r.kind] += t;
+    addn[r.kind] += 1;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  std::lock_guard<std::mutex> lock(g_tr_mu);
+  for (int k = 0; k < TK_COUNT; ++k) {
+    g_tr_ms[k] += add[k];
+    g_tr_n[k] += addn[k];
+  }
+  const int m = std::min(nkinds, (int)TK_COUNT);
+  for (int k = 0; k < m; ++k) {
+    if (ms) ms[k] = g_tr_ms[k];
+    if (count) count[k] = g_tr_n[k];
+  }
+  return st;
+}
+
+const char* kx_trace_name(int kind) {
+  if (kind < 0 || kind >= TK_COUNT) return "";
+  return kTraceNames[kind];
+}
 
 kx_status kx_host_fd_weights(int fd_order, double* c) {
   if (fd_order < 2 || fd_order > 16 || fd_order % 2) return fail(KX_EINVAL, "fd_order must be even in [2, 16]");
@@ -483,24 +614,31 @@ kx_status kron_solve(kx_plan p, const void* B, int64_t ldb, void* X, int64_t ldx
   C.V1 = p->dVmat[0]; C.V2 = p->dVmat[1]; C.P = p->P12;
   const int64_t items = (int64_t)nrhs * p->n[2];
   hipError_t e;
+  const int mb = p->max_blocks;
   if (path == KX_PATH_FUSED) {
-    e = f64 ? launch_slice_fwd_f64(p->nk12, SF_LOAD12, A, items, p->max_blocks, s)
-            : launch_slice_fwd_f32(p->nk12, SF_LOAD12, A, items, p->max_blocks, s);
+    e = traced(TK_S_A, s, [&] {
+      return f64 ? launch_slice_fwd_f64(p->nk12, SF_LOAD12, A, items, mb, s)
+                 : launch_slice_fwd_f32(p->nk12, SF_LOAD12, A, items, mb, s);
+    });
     if (e == hipSuccess)
-      e = f64 ? launch_pencil_f64(p->nk3, PC_FSI, Pn, p->max_blocks, s)
-              : launch_pencil_f32(p->nk3, PC_FSI, Pn, p->max_blocks, s);
+      e = traced(TK_S_B, s, [&] {
+        return f64 ? launch_pencil_f64(p->nk3, PC_FSI, Pn, mb, s) : launch_pencil_f32(p->nk3, PC_FSI, Pn, mb, s);
+      });
     if (e == hipSuccess)
-      e = f64 ? launch_slice_inv_f64(p->nk12, SI_ST12, C, items, p->max_blocks, s)
-              : launch_slice_inv_f32(p->nk12, SI_ST12, C, items, p->max_blocks, s);
+      e = traced(TK_S_C, s, [&] {
+        return f64 ? launch_slice_inv_f64(p->nk12, SI_ST12, C, items, mb, s)
+                   : launch_slice_inv_f32(p->nk12, SI_ST12, C, items, mb, s);
+      });
   } else {
-    e = launch_slice_fwd_f64(p->nk12, SF_LOAD1, A, items, p->max_blocks, s);
+    e = traced(TK_SP_M1F, s, [&] { return launch_slice_fwd_f64(p->nk12, SF_LOAD1, A, items, mb, s); });
     A.src = X; A.ld_src = ldx;
-    if (e == hipSuccess) e = launch_slice_fwd_f64(p->nk12, SF_LOAD2, A, items, p->max_blocks, s);
-    if (e == hipSuccess) e = launch_pencil_f64(p->nk3, PC_F, Pn, p->max_blocks, s);
-    if (e == hipSuccess) e = launch_scale_f64((double*)X, ldx, nrhs, p->N, p->d_f, s);
-    if (e == hipSuccess) e = launch_pencil_f64(p->nk3, PC_I, Pn, p->max_blocks, s);
-    if (e == hipSuccess) e = launch_slice_inv_f64(p->nk12, SI_ST2, C, items, p->max_blocks, s);
-    if (e == hipSuccess) e = launch_slice_inv_f64(p->nk12, SI_ST1, C, items, p->max_blocks, s);
+    if (e == hipSuccess) e = traced(TK_SP_M2F, s, [&] { return launch_slice_fwd_f64(p->nk12, SF_LOAD2, A, items, mb, s); });
+    if (e == hipSuccess) e = traced(TK_SP_M3F, s, [&] { return launch_pencil_f64(p->nk3, PC_F, Pn, mb, s); });
+    if (e == hipSuccess)
+      e = traced(TK_SP_SCALE, s, [&] { return launch_scale_f64((double*)X, ldx, nrhs, p->N, p->d_f, s); });
+    if (e == hipSuccess) e = traced(TK_SP_M3I, s, [&] { return launch_pencil_f64(p->nk3, PC_I, Pn, mb, s); });
+    if (e == hipSuccess) e = traced(TK_SP_M2I, s, [&] { return launch_slice_inv_f64(p->nk12, SI_ST2, C, items, mb, s); });
+    if (e == hipSuccess) e = traced(TK_SP_M1I, s, [&] { return launch_slice_inv_f64(p->nk12, SI_ST1, C, items, mb, s); });
   }
   if (e != hipSuccess) return dev_fail(e, "kron_solve launch");
   return KX_OK;
@@ -554,16 +692,25 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
       return KX_OK;
     }
   }
+  // Capture on a private stream (capture is not allowed on the legacy default
+  // stream); the instantiated graph is launched on the caller's stream.
   hipGraph_t graph = nullptr;
-  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return dev_fail(e, "exx_apply_batched capture");
+  hipStream_t cap = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return dev_fail(e, "exx_apply_batched capture stream");
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    hipStreamDestroy(cap);
+    return dev_fail(e, "exx_apply_batched capture");
+  }
   kx_status st = KX_OK;
   for (int i = 0; i < ntasks && st == KX_OK; ++i) {
     const kx_task& t = tasks[i];
     st = enqueue_exx(t.plan, t.d_psi, t.ld_psi, t.n_occ, t.d_occ, t.d_phi, t.ld_phi, t.n_b, t.d_vx,
-                     t.ld_vx, t.d_ex, t.d_gphi, KX_PATH_FUSED, s);
+                     t.ld_vx, t.d_ex, t.d_gphi, KX_PATH_FUSED, cap);
   }
-  e = hipStreamEndCapture(s, &graph);
+  e = hipStreamEndCapture(cap, &graph);
+  hipStreamDestroy(cap);
   if (st != KX_OK) {
     if (graph) hipGraphDestroy(graph);
     return st;

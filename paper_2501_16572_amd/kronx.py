@@ -31,7 +31,7 @@ PATH = {"fused": 0, "plain": 1}
 # Every symbol declared in include/kronx.h.
 EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_batched",
            "kx_plan_info", "kx_plan_tables", "kx_host_eig1d", "kx_host_fd_weights",
-           "kx_last_error"]
+           "kx_last_error", "kx_trace_enable", "kx_trace_read", "kx_trace_name"]
 
 
 class KronxError(RuntimeError):
@@ -74,8 +74,12 @@ def load_library(path=None):
     lib.kx_host_eig1d.argtypes = [ci, cd, ci, ci, cd, dp, dp, dp]
     lib.kx_host_fd_weights.argtypes = [ci, dp]
     lib.kx_last_error.restype = ctypes.c_char_p
+    lib.kx_trace_enable.argtypes = [ci]
+    lib.kx_trace_read.argtypes = [dp, i64p, ci]
+    lib.kx_trace_name.argtypes = [ci]
+    lib.kx_trace_name.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name != "kx_last_error":
+        if name not in ("kx_last_error", "kx_trace_name"):
             getattr(lib, name).restype = ci
     _lib = lib
     return lib
@@ -217,6 +221,22 @@ def exx_apply_batched(tasks, stream=None):
                        t["phi"].shape[0], pv, ldv, ex.data_ptr() if ex is not None else None,
                        gphi.data_ptr() if gphi is not None else None)
     _check(load_library().exx_apply_batched(arr, len(tasks), _stream(stream)), "exx_apply_batched")
+
+
+TRACE_KINDS = 23
+
+
+def kx_trace_enable(on=True):
+    _check(load_library().kx_trace_enable(1 if on else 0), "kx_trace_enable")
+
+
+def kx_trace_read():
+    """{kind name: (total ms, launches)} for every kind launched since enabling."""
+    lib = load_library()
+    ms = (ctypes.c_double * TRACE_KINDS)()
+    cnt = (ctypes.c_int64 * TRACE_KINDS)()
+    _check(lib.kx_trace_read(ms, cnt, TRACE_KINDS), "kx_trace_read")
+    return {lib.kx_trace_name(k).decode(): (ms[k], cnt[k]) for k in range(TRACE_KINDS) if cnt[k]}
 
 
 def kx_host_eig1d(n, h, bc, fd_order=12, kappa=0.0):

@@ -198,11 +198,20 @@ def test_exx_deterministic_and_edge_cases(kx):
         kx.exx_apply(plan, psid, occ, psid[:0], vx0[:0])
         torch.cuda.synchronize()
         assert float(vx0.abs().max()) == 0.0
-        # leading dimension below N is rejected before any work
-        bad = torch.zeros((4, psid.shape[1] - 1), dtype=torch.float64, device="cuda")
-        with pytest.raises(kx.KronxError) as ei:
+        # leading dimension below N is rejected by the library before any work
+        import ctypes
+        lib = kx.load_library()
+        N = psid.shape[1]
+        st = lib.exx_apply(plan.handle, ctypes.c_void_p(psid.data_ptr()), N - 1, 4,
+                           ctypes.c_void_p(occ.data_ptr()), ctypes.c_void_p(psid.data_ptr()), N, 4,
+                           ctypes.c_void_p(vx0.data_ptr()), N, None, None, 0, None)
+        assert st == kx.KX_EINVAL
+        # and a malformed tensor never reaches it
+        bad = torch.zeros((4, N - 1), dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError):
             kx.exx_apply(plan, bad, occ, psid, vx0)
-        assert ei.value.status == kx.KX_EINVAL
+        torch.cuda.synchronize()
+        assert float(vx0.abs().max()) == 0.0
     finally:
         plan.destroy()
 
