@@ -107,6 +107,9 @@ def main():
                     help="comma list of prec:path; the first one gives `value`")
     ap.add_argument("--cpu-bands", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="copy 1 GiB on the device first: a kernel of known traffic for scaling "
+                         "FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the exchange path of this library is a "
@@ -121,6 +124,12 @@ def main():
     from paper_2501_16572_amd.workloads import CONFIGS, make_inputs
 
     kx.load_library()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = CONFIGS[args.workload]
     n_occ = cfg["n_occ"]
     n1, n2, n3 = cfg["n"]

@@ -171,7 +171,8 @@ struct kx_plan_s {
   std::vector<double> lam[3], Vre[3], Vim[3], f;
   int nk12, nk3, P12, P3;
   int device;
-  void* dVmat[3] = {nullptr, nullptr, nullptr};
+  void* dVmat[3] = {nullptr, nullptr, nullptr};   // padded V_d, V[k*P + a]
+  void* dVmatT[3] = {nullptr, nullptr, nullptr};  // padded V_d^T
   double* d_f = nullptr;
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
@@ -220,8 +221,10 @@ kx_status ensure_buffer(void** ptr, size_t* have, size_t need, const char* what)
 }
 
 void free_plan_device(kx_plan p) {
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < 3; ++d) {
     if (p->dVmat[d]) hipFree(p->dVmat[d]);
+    if (p->dVmatT[d]) hipFree(p->dVmatT[d]);
+  }
   if (p->d_f) hipFree(p->d_f);
   if (p->d_ws) hipFree(p->d_ws);
   if (p->d_part) hipFree(p->d_part);
@@ -301,7 +304,7 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
     PencilArgs B{};
     B.n1 = p->n[0]; B.n2 = p->n[1]; B.n3 = p->n[2]; B.n12 = p->n12;
     B.npairs = npairs; B.nchunks = (p->n12 + 63) / 64;
-    B.T = p->d_ws; B.ld = p->N; B.V3 = p->dVmat[2]; B.P3 = p->P3; B.ftab = p->d_f;
+    B.T = p->d_ws; B.ld = p->N; B.V3 = p->dVmat[2]; B.V3T = p->dVmatT[2]; B.P3 = p->P3; B.ftab = p->d_f;
     AccArgs C{};
     C.n1 = p->n[0]; C.n2 = p->n[1]; C.n3 = p->n[2]; C.n12 = p->n12; C.N = p->N;
     C.n_t = cur; C.n_occ = n_occ;
@@ -311,7 +314,7 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
     C.vx = vx + (size_t)n0 * ld_vx; C.ld_vx = ld_vx;
     C.partials = ex ? p->d_part : nullptr;
     C.dst = p->d_ws; C.ld_dst = p->N;
-    C.V1 = p->dVmat[0]; C.V2 = p->dVmat[1]; C.P = p->P12;
+    C.V1 = p->dVmatT[0]; C.V2 = p->dVmatT[1]; C.P = p->P12;
     const int64_t items_pairs = (int64_t)npairs * p->n[2];
     hipError_t e = hipSuccess;
     int per_target = p->n[2];
@@ -499,17 +502,22 @@ kx_status kron_setup(const int n[3], const double h[3], const int bc[3], int fd_
   for (int d = 0; d < 3; ++d) {
     const int P = d < 2 ? p->P12 : p->P3;
     const int nd = n[d];
-    std::vector<char> host((size_t)P * P * eb, 0);
+    std::vector<char> host((size_t)P * P * eb, 0), hostT((size_t)P * P * eb, 0);
     for (int k = 0; k < nd; ++k)
       for (int a = 0; a < nd; ++a) {
         const double v = p->Vre[d][(size_t)k * nd + a];
-        if (eb == 8)
+        if (eb == 8) {
           ((double*)host.data())[(size_t)k * P + a] = v;
-        else
+          ((double*)hostT.data())[(size_t)a * P + k] = v;
+        } else {
           ((float*)host.data())[(size_t)k * P + a] = (float)v;
+          ((float*)hostT.data())[(size_t)a * P + k] = (float)v;
+        }
       }
     hipError_t e = hipMalloc(&p->dVmat[d], host.size());
     if (e == hipSuccess) e = hipMemcpy(p->dVmat[d], host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p->dVmatT[d], hostT.size());
+    if (e == hipSuccess) e = hipMemcpy(p->dVmatT[d], hostT.data(), hostT.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       free_plan_device(p);
       delete p;
@@ -606,12 +614,12 @@ kx_status kron_solve(kx_plan p, const void* B, int64_t ldb, void* X, int64_t ldx
   PencilArgs Pn{};
   Pn.n1 = p->n[0]; Pn.n2 = p->n[1]; Pn.n3 = p->n[2]; Pn.n12 = p->n12;
   Pn.npairs = nrhs; Pn.nchunks = (p->n12 + 63) / 64;
-  Pn.T = X; Pn.ld = ldx; Pn.V3 = p->dVmat[2]; Pn.P3 = p->P3; Pn.ftab = p->d_f;
+  Pn.T = X; Pn.ld = ldx; Pn.V3 = p->dVmat[2]; Pn.V3T = p->dVmatT[2]; Pn.P3 = p->P3; Pn.ftab = p->d_f;
   AccArgs C{};
   C.n1 = p->n[0]; C.n2 = p->n[1]; C.n3 = p->n[2]; C.n12 = p->n12; C.N = p->N;
   C.n_t = nrhs; C.n_occ = 1;
   C.T = X; C.ld_T = ldx; C.dst = X; C.ld_dst = ldx;
-  C.V1 = p->dVmat[0]; C.V2 = p->dVmat[1]; C.P = p->P12;
+  C.V1 = p->dVmatT[0]; C.V2 = p->dVmatT[1]; C.P = p->P12;
   const int64_t items = (int64_t)nrhs * p->n[2];
   hipError_t e;
   const int mb = p->max_blocks;

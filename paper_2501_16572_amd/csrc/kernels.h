@@ -48,7 +48,8 @@ struct PencilArgs {
   int npairs;
   int nchunks;            // ceil(n12 / Q)
   void* T; int64_t ld;    // in place: T + p*ld
-  const void* V3;         // padded P3 x P3, V[k*P3 + c]
+  const void* V3;         // padded P3 x P3, V3[k*P3 + c]
+  const void* V3T;        // its transpose
   int P3;
   const double* ftab;     // N doubles, f(lambda) in the flat grid order
 };
@@ -65,7 +66,7 @@ struct AccArgs {
   double* vx; int64_t ld_vx;         // target t of this batch at vx + t*ld_vx
   double* partials;                  // n_t * n3 doubles (E_x partials) or null
   void* dst; int64_t ld_dst;         // solve mode: Y stored at dst + p*ld_dst
-  const void* V1; const void* V2;
+  const void* V1; const void* V2;    // TRANSPOSED padded matrices V1^T, V2^T
   int P;
 };
 
