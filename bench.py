@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="hse72")
-    ap.add_argument("--forms", default="fp64:fused,fp64:plain,fp32:fused",
+    ap.add_argument("--forms", default="fp64:fused,fp64:plain,fp32:fused,bf16x6:fused,bf16x3:fused",
                     help="comma list of prec:path; the first one gives `value`")
     ap.add_argument("--cpu-bands", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")

@@ -74,6 +74,12 @@ enum { KX_BC_PERIODIC = 0, KX_BC_DIRICHLET = 1 };
  *            relative weight 2^-16. */
 enum { KX_PREC_FP64 = 0, KX_PREC_FP32 = 1, KX_PREC_BF16X3 = 2, KX_PREC_BF16X6 = 3 };
 
+/* OR-ed into kron_setup's prec: complex data even when k - q = 0 (the k = q
+ * blocks of a k-point calculation, whose orbitals are complex Bloch functions
+ * although the pair problem is plain periodic).  Complex plans run in FP64
+ * (complex128) or FP32 (complex64). */
+enum { KX_FLAG_COMPLEX = 16 };
+
 /* Kernel organisation for exx_apply / kron_solve.
  *   FUSED : three passes per batch -- (A) pair density + mode-1 + mode-2
  *           forward on frontal slices, (B) mode-3 forward, eigen-scaling,
@@ -95,7 +101,7 @@ enum { KX_PATH_FUSED = 0, KX_PATH_PLAIN = 1 };
  *   kq[3]     Bloch wavevector k - q (bohr^-1) per axis, or NULL for zero.
  *             A nonzero component requires a periodic axis and makes the
  *             plan complex.
- *   prec      KX_PREC_*.
+ *   prec      KX_PREC_*, optionally | KX_FLAG_COMPLEX.
  *   out       receives the plan.  On error *out is set to NULL.
  * Host-side FP64 work (weights, eigenpairs, f table), then device uploads on
  * the current device (synchronous).  The plan is immutable afterwards and may

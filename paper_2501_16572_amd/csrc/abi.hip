@@ -173,6 +173,10 @@ struct kx_plan_s {
   int device;
   void* dVmat[3] = {nullptr, nullptr, nullptr};   // padded V_d, V[k*P + a]
   void* dVmatT[3] = {nullptr, nullptr, nullptr};  // padded V_d^T
+  // split-BF16 eigenvector parts, [c][k] with K contiguous:
+  // [d][0] = split(V_d^T) (forward products), [d][1] = split(V_d) (inverse)
+  void* dVbf[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int bf_nt12 = 0, bf_nt3 = 0, bf_vps12 = 0, bf_vps3 = 0, bf_kp12 = 0, bf_kp3 = 0;
   double* d_f = nullptr;
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
@@ -224,6 +228,8 @@ void free_plan_device(kx_plan p) {
   for (int d = 0; d < 3; ++d) {
     if (p->dVmat[d]) hipFree(p->dVmat[d]);
     if (p->dVmatT[d]) hipFree(p->dVmatT[d]);
+    for (int k = 0; k < 2; ++k)
+      if (p->dVbf[d][k]) hipFree(p->dVbf[d][k]);
   }
   if (p->d_f) hipFree(p->d_f);
   if (p->d_ws) hipFree(p->d_ws);
@@ -248,10 +254,48 @@ kx_status check_exx_args(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, 
   const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);
   if (((uintptr_t)psi % eb) || ((uintptr_t)phi % eb) || ((uintptr_t)vx % 8) || ((uintptr_t)occ % 8))
     return fail(KX_EINVAL, "exx_apply: misaligned pointer");
-  if (p->cplx) return fail(KX_EUNSUPPORTED, "exx_apply: complex (Bloch) plans are not built yet");
-  if (p->prec == KX_PREC_BF16X3 || p->prec == KX_PREC_BF16X6)
-    return fail(KX_EUNSUPPORTED, "exx_apply: split-BF16 precision is not built yet");
+  if (p->cplx && path == KX_PATH_PLAIN)
+    return fail(KX_EUNSUPPORTED, "exx_apply: the plain path is real (Gamma) only");
   return KX_OK;
+}
+
+// Precision dispatch of the three fused passes.
+bool is_bf(const kx_plan p) { return p->prec == KX_PREC_BF16X3 || p->prec == KX_PREC_BF16X6; }
+int bf_spl(const kx_plan p) { return p->prec == KX_PREC_BF16X3 ? 2 : 3; }
+
+hipError_t launch_pass_a(kx_plan p, int variant, const kx::SliceArgs& A, int64_t items, hipStream_t s) {
+  using namespace kx;
+  if (p->cplx) return launch_slice_fwd_c(p->prec == KX_PREC_FP64, p->nk12, variant, A, items, p->max_blocks, s);
+  if (p->prec == KX_PREC_FP64) return launch_slice_fwd_f64(p->nk12, variant, A, items, p->max_blocks, s);
+  if (p->prec == KX_PREC_FP32) return launch_slice_fwd_f32(p->nk12, variant, A, items, p->max_blocks, s);
+  SliceArgs Ab = A;
+  Ab.V1 = p->dVbf[0][0];
+  Ab.V2 = p->dVbf[1][0];
+  return launch_slice_fwd_bf(bf_spl(p), p->bf_nt12, variant, Ab, items, p->max_blocks, p->bf_vps12,
+                             p->bf_kp12, s);
+}
+
+hipError_t launch_pass_b(kx_plan p, const kx::PencilArgs& B, hipStream_t s) {
+  using namespace kx;
+  if (p->cplx) return launch_pencil_c(p->prec == KX_PREC_FP64, p->nk3, B, p->max_blocks, s);
+  if (p->prec == KX_PREC_FP64) return launch_pencil_f64(p->nk3, PC_FSI, B, p->max_blocks, s);
+  if (p->prec == KX_PREC_FP32) return launch_pencil_f32(p->nk3, PC_FSI, B, p->max_blocks, s);
+  PencilArgs Bb = B;
+  Bb.V3 = p->dVbf[2][0];
+  Bb.V3T = p->dVbf[2][1];
+  return launch_pencil_bf(bf_spl(p), p->bf_nt3, Bb, p->max_blocks, p->bf_vps3, p->bf_kp3, s);
+}
+
+hipError_t launch_pass_c(kx_plan p, int variant, const kx::AccArgs& C, int64_t items, hipStream_t s) {
+  using namespace kx;
+  if (p->cplx) return launch_slice_inv_c(p->prec == KX_PREC_FP64, p->nk12, variant, C, items, p->max_blocks, s);
+  if (p->prec == KX_PREC_FP64) return launch_slice_inv_f64(p->nk12, variant, C, items, p->max_blocks, s);
+  if (p->prec == KX_PREC_FP32) return launch_slice_inv_f32(p->nk12, variant, C, items, p->max_blocks, s);
+  AccArgs Cb = C;
+  Cb.V1 = p->dVbf[0][1];
+  Cb.V2 = p->dVbf[1][1];
+  return launch_slice_inv_bf(bf_spl(p), p->bf_nt12, variant, Cb, items, p->max_blocks, p->bf_vps12,
+                             p->bf_kp12, s);
 }
 
 // Enqueue one exx_apply.  Arguments already validated; buffers allocated for
@@ -288,8 +332,8 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
   const int nt = (int)std::min<size_t>(cap, (size_t)n_b);
   if (nt < 1) return fail(KX_ESTATE, "exx_apply: workspace not prepared");
   p->last_nt = nt;
-  const size_t eb = elem_bytes(p->prec);
-  const bool f64 = p->prec == KX_PREC_FP64;
+  const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);  // bytes per grid value
+  const size_t vxw = p->cplx ? 2 : 1;                          // doubles per Vx value
   for (int n0 = 0; n0 < n_b; n0 += nt) {
     const int cur = std::min(nt, n_b - n0);
     const int npairs = cur * n_occ;
@@ -311,7 +355,7 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
     C.T = p->d_ws; C.ld_T = p->N;
     C.psi = psi; C.ld_psi = ld_psi; C.occ = occ;
     C.phi = phi0; C.ld_phi = ld_phi;
-    C.vx = vx + (size_t)n0 * ld_vx; C.ld_vx = ld_vx;
+    C.vx = vx + (size_t)n0 * ld_vx * vxw; C.ld_vx = ld_vx;
     C.partials = ex ? p->d_part : nullptr;
     C.dst = p->d_ws; C.ld_dst = p->N;
     C.V1 = p->dVmatT[0]; C.V2 = p->dVmatT[1]; C.P = p->P12;
@@ -319,21 +363,10 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
     hipError_t e = hipSuccess;
     int per_target = p->n[2];
     if (path == KX_PATH_FUSED) {
-      e = traced(TK_A, s, [&] {
-        return f64 ? launch_slice_fwd_f64(p->nk12, SF_PAIR12, A, items_pairs, p->max_blocks, s)
-                   : launch_slice_fwd_f32(p->nk12, SF_PAIR12, A, items_pairs, p->max_blocks, s);
-      });
+      e = traced(TK_A, s, [&] { return launch_pass_a(p, SF_PAIR12, A, items_pairs, s); });
+      if (e == hipSuccess) e = traced(TK_B, s, [&] { return launch_pass_b(p, B, s); });
       if (e == hipSuccess)
-        e = traced(TK_B, s, [&] {
-          return f64 ? launch_pencil_f64(p->nk3, PC_FSI, B, p->max_blocks, s)
-                     : launch_pencil_f32(p->nk3, PC_FSI, B, p->max_blocks, s);
-        });
-      if (e == hipSuccess)
-        e = traced(TK_C, s, [&] {
-          const int64_t it = (int64_t)cur * p->n[2];
-          return f64 ? launch_slice_inv_f64(p->nk12, SI_ACC12, C, it, p->max_blocks, s)
-                     : launch_slice_inv_f32(p->nk12, SI_ACC12, C, it, p->max_blocks, s);
-        });
+        e = traced(TK_C, s, [&] { return launch_pass_c(p, SI_ACC12, C, (int64_t)cur * p->n[2], s); });
     } else {
       // plain FP64: one kernel per step, each a full pass over the batch
       const int mb = p->max_blocks;
@@ -360,6 +393,41 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
     if (e != hipSuccess) return dev_fail(e, "exx_apply launch");
   }
   return KX_OK;
+}
+
+// Round to bf16 (nearest even) through FP32; returns the bf16 bit pattern and
+// its value.
+uint16_t to_bf16(double v, double* back) {
+  float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  const uint16_t h = (uint16_t)(u >> 16);
+  uint32_t w = (uint32_t)h << 16;
+  float g;
+  std::memcpy(&g, &w, 4);
+  *back = g;
+  return h;
+}
+
+// Upload the split parts of M (n x n, M[r*n + c]) as [c][k] = M^T or M:
+// transpose == true stores part(M[k][c]) at [c][k]; false stores part(M[c][k]).
+// Layout: nparts x rows x kp bf16 values, zero outside n x n.
+hipError_t upload_bf_parts(const std::vector<double>& M, int n, bool transpose, int nparts,
+                           int rows, int kp, void** out) {
+  std::vector<uint16_t> h((size_t)nparts * rows * kp, 0);
+  for (int c = 0; c < n; ++c)
+    for (int k = 0; k < n; ++k) {
+      double v = transpose ? M[(size_t)k * n + c] : M[(size_t)c * n + k];
+      for (int q = 0; q < nparts; ++q) {
+        double b;
+        h[((size_t)q * rows + c) * kp + k] = to_bf16(v, &b);
+        v -= b;
+      }
+    }
+  hipError_t e = hipMalloc(out, h.size() * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMemcpy(*out, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  return e;
 }
 
 }  // namespace
@@ -468,9 +536,21 @@ kx_status kron_setup(const int n[3], const double h[3], const int bc[3], int fd_
   if (fd_order < 2 || fd_order > 16 || fd_order % 2)
     return fail(KX_EINVAL, "kron_setup: fd_order must be even in [2, 16]");
   if (!std::isfinite(omega)) return fail(KX_EINVAL, "kron_setup: omega is not finite");
+  const bool force_cplx = (prec & KX_FLAG_COMPLEX) != 0;
+  prec &= ~KX_FLAG_COMPLEX;
   if (prec < KX_PREC_FP64 || prec > KX_PREC_BF16X6) return fail(KX_EINVAL, "kron_setup: unknown precision %d", prec);
   if (prec == KX_PREC_FP64 && std::max(n[0], n[1]) > 128)
     return fail(KX_EUNSUPPORTED, "kron_setup: FP64 slices are limited to n1, n2 <= 128 (LDS)");
+  {
+    const bool cplx = force_cplx || (kq && (kq[0] != 0.0 || kq[1] != 0.0 || kq[2] != 0.0));
+    if (cplx && prec != KX_PREC_FP64 && prec != KX_PREC_FP32)
+      return fail(KX_EUNSUPPORTED, "kron_setup: complex (Bloch) plans run in FP64 or FP32");
+    if (cplx && prec == KX_PREC_FP64 && n[2] > 144)
+      return fail(KX_EUNSUPPORTED, "kron_setup: complex FP64 pencils are limited to n3 <= 144 (LDS)");
+    if (cplx && std::max(n[0], n[1]) > (prec == KX_PREC_FP64 ? 96 : 128))
+      return fail(KX_EUNSUPPORTED, "kron_setup: complex slices are limited to n1, n2 <= %d (LDS)",
+                  prec == KX_PREC_FP64 ? 96 : 128);
+  }
 
   kx_plan p = new (std::nothrow) kx_plan_s();
   if (!p) return fail(KX_ENOMEM, "kron_setup: host allocation");
@@ -483,7 +563,7 @@ kx_status kron_setup(const int n[3], const double h[3], const int bc[3], int fd_
   p->order = fd_order;
   p->omega = omega;
   p->prec = prec;
-  p->cplx = p->kq[0] != 0.0 || p->kq[1] != 0.0 || p->kq[2] != 0.0;
+  p->cplx = force_cplx || p->kq[0] != 0.0 || p->kq[1] != 0.0 || p->kq[2] != 0.0;
   p->N = (int64_t)n[0] * n[1] * n[2];
   p->n12 = n[0] * n[1];
   p->dV = h[0] * h[1] * h[2];
@@ -502,18 +582,22 @@ kx_status kron_setup(const int n[3], const double h[3], const int bc[3], int fd_
   for (int d = 0; d < 3; ++d) {
     const int P = d < 2 ? p->P12 : p->P3;
     const int nd = n[d];
-    std::vector<char> host((size_t)P * P * eb, 0), hostT((size_t)P * P * eb, 0);
-    for (int k = 0; k < nd; ++k)
-      for (int a = 0; a < nd; ++a) {
-        const double v = p->Vre[d][(size_t)k * nd + a];
-        if (eb == 8) {
-          ((double*)host.data())[(size_t)k * P + a] = v;
-          ((double*)hostT.data())[(size_t)a * P + k] = v;
-        } else {
-          ((float*)host.data())[(size_t)k * P + a] = (float)v;
-          ((float*)hostT.data())[(size_t)a * P + k] = (float)v;
+    // real plans: one plane; complex plans: re plane then im plane
+    const int planes = p->cplx ? 2 : 1;
+    std::vector<char> host((size_t)planes * P * P * eb, 0), hostT((size_t)planes * P * P * eb, 0);
+    for (int pl = 0; pl < planes; ++pl)
+      for (int k = 0; k < nd; ++k)
+        for (int a = 0; a < nd; ++a) {
+          const double v = (pl == 0 ? p->Vre[d] : p->Vim[d])[(size_t)k * nd + a];
+          const size_t o = (size_t)pl * P * P;
+          if (eb == 8) {
+            ((double*)host.data())[o + (size_t)k * P + a] = v;
+            ((double*)hostT.data())[o + (size_t)a * P + k] = v;
+          } else {
+            ((float*)host.data())[o + (size_t)k * P + a] = (float)v;
+            ((float*)hostT.data())[o + (size_t)a * P + k] = (float)v;
+          }
         }
-      }
     hipError_t e = hipMalloc(&p->dVmat[d], host.size());
     if (e == hipSuccess) e = hipMemcpy(p->dVmat[d], host.data(), host.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&p->dVmatT[d], hostT.size());
@@ -527,10 +611,25 @@ kx_status kron_setup(const int n[3], const double h[3], const int bc[3], int fd_
   }
   hipError_t e = hipMalloc((void**)&p->d_f, p->f.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(p->d_f, p->f.data(), p->f.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess && (prec == KX_PREC_BF16X3 || prec == KX_PREC_BF16X6)) {
+    const int parts = prec == KX_PREC_BF16X3 ? 2 : 3;
+    p->bf_nt12 = kx::bf_nt(std::max(n[0], n[1]));
+    p->bf_nt3 = kx::bf_nt(n[2]);
+    p->bf_kp12 = kx::bf_kp(p->bf_nt12);
+    p->bf_kp3 = kx::bf_kp(p->bf_nt3);
+    const int rows12 = kx::bf_lines(p->bf_nt12), rows3 = kx::bf_lines(p->bf_nt3);
+    p->bf_vps12 = rows12 * p->bf_kp12;
+    p->bf_vps3 = rows3 * p->bf_kp3;
+    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+      const int rows = d < 2 ? rows12 : rows3, kp = d < 2 ? p->bf_kp12 : p->bf_kp3;
+      e = upload_bf_parts(p->Vre[d], n[d], true, parts, rows, kp, &p->dVbf[d][0]);
+      if (e == hipSuccess) e = upload_bf_parts(p->Vre[d], n[d], false, parts, rows, kp, &p->dVbf[d][1]);
+    }
+  }
   if (e != hipSuccess) {
     free_plan_device(p);
     delete p;
-    return dev_fail(e, "kron_setup f table");
+    return dev_fail(e, "kron_setup tables");
   }
   *out = p;
   return KX_OK;
@@ -593,10 +692,9 @@ kx_status kron_solve(kx_plan p, const void* B, int64_t ldb, void* X, int64_t ldx
   if (nrhs == 0) return KX_OK;
   if (!B || !X) return fail(KX_EINVAL, "kron_solve: NULL data pointer");
   if (ldb < p->N || ldx < p->N) return fail(KX_EINVAL, "kron_solve: leading dimension below N");
-  if (p->cplx) return fail(KX_EUNSUPPORTED, "kron_solve: complex (Bloch) plans are not built yet");
-  if (p->prec == KX_PREC_BF16X3 || p->prec == KX_PREC_BF16X6)
-    return fail(KX_EUNSUPPORTED, "kron_solve: split-BF16 precision is not built yet");
-  const size_t eb = elem_bytes(p->prec);
+  if (p->cplx && path == KX_PATH_PLAIN)
+    return fail(KX_EUNSUPPORTED, "kron_solve: the plain path is real (Gamma) only");
+  const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);
   {
     const char* b0 = (const char*)B;
     const char* b1 = b0 + ((size_t)(nrhs - 1) * ldb + p->N) * eb;
@@ -605,7 +703,6 @@ kx_status kron_solve(kx_plan p, const void* B, int64_t ldb, void* X, int64_t ldx
     if (b0 < x1 && x0 < b1) return fail(KX_EINVAL, "kron_solve: B and X overlap");
   }
   hipStream_t s = (hipStream_t)stream;
-  const bool f64 = p->prec == KX_PREC_FP64;
   SliceArgs A{};
   A.n1 = p->n[0]; A.n2 = p->n[1]; A.n3 = p->n[2]; A.n12 = p->n12; A.N = p->N;
   A.npairs = nrhs; A.n_occ = 1;
@@ -624,19 +721,9 @@ kx_status kron_solve(kx_plan p, const void* B, int64_t ldb, void* X, int64_t ldx
   hipError_t e;
   const int mb = p->max_blocks;
   if (path == KX_PATH_FUSED) {
-    e = traced(TK_S_A, s, [&] {
-      return f64 ? launch_slice_fwd_f64(p->nk12, SF_LOAD12, A, items, mb, s)
-                 : launch_slice_fwd_f32(p->nk12, SF_LOAD12, A, items, mb, s);
-    });
-    if (e == hipSuccess)
-      e = traced(TK_S_B, s, [&] {
-        return f64 ? launch_pencil_f64(p->nk3, PC_FSI, Pn, mb, s) : launch_pencil_f32(p->nk3, PC_FSI, Pn, mb, s);
-      });
-    if (e == hipSuccess)
-      e = traced(TK_S_C, s, [&] {
-        return f64 ? launch_slice_inv_f64(p->nk12, SI_ST12, C, items, mb, s)
-                   : launch_slice_inv_f32(p->nk12, SI_ST12, C, items, mb, s);
-      });
+    e = traced(TK_S_A, s, [&] { return launch_pass_a(p, SF_LOAD12, A, items, s); });
+    if (e == hipSuccess) e = traced(TK_S_B, s, [&] { return launch_pass_b(p, Pn, s); });
+    if (e == hipSuccess) e = traced(TK_S_C, s, [&] { return launch_pass_c(p, SI_ST12, C, items, s); });
   } else {
     e = traced(TK_SP_M1F, s, [&] { return launch_slice_fwd_f64(p->nk12, SF_LOAD1, A, items, mb, s); });
     A.src = X; A.ld_src = ldx;

@@ -43,6 +43,27 @@ hipError_t launch_accumulate_f64(const AccArgs& a, int blocks_per_target, hipStr
 hipError_t launch_ex_finalize(const double* partials, int n_t, int per_target,
                               const double* gphi, double dV, double* ex, hipStream_t s);
 
+// Split-BF16 launchers (spl = 2 for BF16X3, 3 for BF16X6; nt = 16-wide tiles
+// per padded axis).  vps: element stride between the split parts of one
+// eigenvector operand; kpv: its K padding (32 * ceil(nt / 2)).
+hipError_t launch_slice_fwd_bf(int spl, int nt, int variant, const SliceArgs& a, int64_t items,
+                               int max_blocks, int vps, int kpv, hipStream_t s);
+hipError_t launch_pencil_bf(int spl, int nt, const PencilArgs& a, int max_blocks, int vps, int kpv,
+                            hipStream_t s);
+hipError_t launch_slice_inv_bf(int spl, int nt, int variant, const AccArgs& a, int64_t items,
+                               int max_blocks, int vps, int kpv, hipStream_t s);
+inline int bf_nt(int n) { return (n + 15) / 16; }
+inline int bf_kp(int nt) { return 32 * ((nt + 1) / 2); }
+inline int bf_lines(int nt) { return 16 * nt > bf_kp(nt) ? 16 * nt : bf_kp(nt); }
+
+// Complex (Bloch) launchers: f64 selects complex128 data (else complex64).
+// V arguments point at (re, im) planes, each P x P.
+hipError_t launch_slice_fwd_c(bool f64, int nk, int variant, const SliceArgs& a, int64_t items,
+                              int max_blocks, hipStream_t s);
+hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks, hipStream_t s);
+hipError_t launch_slice_inv_c(bool f64, int nk, int variant, const AccArgs& a, int64_t items,
+                              int max_blocks, hipStream_t s);
+
 // Number of compute units of the current device (cached).
 int device_cu_count();
 

@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "KX_OK", 1: "KX_EINVAL", 2: "KX_EUNSUPPORTED", 3: "KX_ENOMEM"
 BC = {"periodic": 0, "dirichlet": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 PATH = {"fused": 0, "plain": 1}
+FLAG_COMPLEX = 16
 
 # Every symbol declared in include/kronx.h.
 EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_batched",
@@ -108,11 +109,11 @@ def _stream(stream):
 class Plan:
     """Handle of a kx_plan (kron_setup's output)."""
 
-    def __init__(self, handle, n, h, bc, order, omega, kq, prec):
+    def __init__(self, handle, n, h, bc, order, omega, kq, prec, complex_=False):
         self.handle = handle
         self.n, self.h, self.bc = tuple(n), tuple(h), tuple(bc)
         self.order, self.omega, self.kq, self.prec = order, omega, tuple(kq), prec
-        self.complex = any(k != 0.0 for k in self.kq)
+        self.complex = complex_ or any(k != 0.0 for k in self.kq)
         self.N = int(np.prod(self.n))
         self.dV = float(np.prod(self.h))
 
@@ -154,15 +155,19 @@ class Plan:
             self.handle = None
 
 
-def kron_setup(n, h, bc=("periodic",) * 3, fd_order=12, omega=0.0, kq=None, prec="fp64"):
+def kron_setup(n, h, bc=("periodic",) * 3, fd_order=12, omega=0.0, kq=None, prec="fp64",
+               complex=False):
+    """Plan for X = f(L) B.  complex=True forces complex data at k - q = 0."""
     lib = load_library()
     bcs = [BC[b] if isinstance(b, str) else int(b) for b in bc]
     kqv = (ctypes.c_double * 3)(*kq) if kq is not None else None
     handle = ctypes.c_void_p()
     st = lib.kron_setup((ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*h), (ctypes.c_int * 3)(*bcs),
-                        int(fd_order), float(omega), kqv, PREC[prec], ctypes.byref(handle))
+                        int(fd_order), float(omega), kqv, PREC[prec] | (FLAG_COMPLEX if complex else 0),
+                        ctypes.byref(handle))
     _check(st, "kron_setup")
-    return Plan(handle, n, h, bc, fd_order, omega, kq if kq is not None else (0.0, 0.0, 0.0), prec)
+    return Plan(handle, n, h, bc, fd_order, omega, kq if kq is not None else (0.0, 0.0, 0.0), prec,
+                complex_=complex)
 
 
 def kron_destroy(plan):
