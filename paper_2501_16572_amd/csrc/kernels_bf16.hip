@@ -29,6 +29,15 @@
 
 namespace kx {
 
+// Block barrier for LDS hand-offs only: waits for this wave's LDS operations
+// and meets the other waves, but leaves global loads in flight (a full
+// __syncthreads() also waits for them, which would serialize the prefetch of
+// the next work unit with the current one's MFMA work).  Nothing in these
+// kernels communicates through global memory within a block.
+__device__ __forceinline__ void lds_barrier_bf() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
 namespace {
@@ -135,13 +144,13 @@ __device__ __forceinline__ double block_sum_bf(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) red[w] = v;
-  __syncthreads();
+  lds_barrier_bf();
   double s = 0.0;
   if (threadIdx.x == 0) {
     const int nw = blockDim.x >> 6;
     for (int i = 0; i < nw; ++i) s += red[i];
   }
-  __syncthreads();
+  lds_barrier_bf();
   return s;
 }
 
@@ -168,7 +177,7 @@ k_slice_fwd_bf(SliceArgs a, int vpart_stride, int KPV) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
   for (int i = tid; i < SPL * PLANE; i += nthr) S[i] = (__bf16)0.f;
-  __syncthreads();
+  lds_barrier_bf();
   const int nk32 = (max(a.n1, a.n2) + 31) / 32;
   const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
   constexpr int EPT0 = (G::P * G::P + 64 * NW - 1) / (64 * NW);
@@ -212,7 +221,7 @@ k_slice_fwd_bf(SliceArgs a, int vpart_stride, int KPV) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier_bf();
     // mode 1: T1[a][j] = sum_k V1^T[a][k] rho[k][j]; wave strips a = 16(w*SPW + jj)
     f4_t acc[SPW][NT];
 #pragma unroll
@@ -223,7 +232,7 @@ k_slice_fwd_bf(SliceArgs a, int vpart_stride, int KPV) {
     if (c0 < G::P)
       strip_gemm_bf<SPL, SPW, NT, LD, PLANE, true>(acc, S, (const __bf16*)a.V1, vpart_stride, KPV,
                                                    c0, nk32, lr, lg);
-    __syncthreads();
+    lds_barrier_bf();
     // T1 back into the planes as [line a][k = j]
     if (c0 < G::P) {
 #pragma unroll
@@ -236,7 +245,7 @@ k_slice_fwd_bf(SliceArgs a, int vpart_stride, int KPV) {
             if (arow < G::P) put<SPL, LD, PLANE>(S, arow, 16 * t + lr, acc[j][t][r]);
           }
     }
-    __syncthreads();
+    lds_barrier_bf();
     // mode 2: T2[a][b] = sum_k T1[a][k] V2[k][b]; wave strips b
 #pragma unroll
     for (int j = 0; j < SPW; ++j)
@@ -258,7 +267,7 @@ k_slice_fwd_bf(SliceArgs a, int vpart_stride, int KPV) {
           }
       }
     }
-    __syncthreads();
+    lds_barrier_bf();
   }
 }
 
@@ -295,7 +304,7 @@ k_pencil_bf(PencilArgs a, int vpart_stride, int KPV) {
         fr[j][qt][r] = (q < a.n12 && c < a.n3) ? a.ftab[q + (int64_t)a.n12 * c] : 0.0;
       }
   }
-  __syncthreads();
+  lds_barrier_bf();
   constexpr int EPT0 = (Q * G::P + 64 * NW - 1) / (64 * NW);
   constexpr int CH = EPT0 < 16 ? EPT0 : 16;
   constexpr int EPT = (EPT0 + CH - 1) / CH * CH;
@@ -316,7 +325,7 @@ k_pencil_bf(PencilArgs a, int vpart_stride, int KPV) {
         if (k < a.n3) put<SPL, LD, PLANE>(S, qq, k, v[j]);  // line q, k = i3
       }
     }
-    __syncthreads();
+    lds_barrier_bf();
     f4_t acc[SPW][QT];
 #pragma unroll
     for (int j = 0; j < SPW; ++j)
@@ -325,7 +334,7 @@ k_pencil_bf(PencilArgs a, int vpart_stride, int KPV) {
     if (c0 < G::P)
       strip_gemm_bf<SPL, SPW, QT, LD, PLANE, false>(acc, S, (const __bf16*)a.V3, vpart_stride,
                                                     KPV, c0, nk32, lr, lg);
-    __syncthreads();
+    lds_barrier_bf();
     if (c0 < G::P) {
 #pragma unroll
       for (int j = 0; j < SPW; ++j) {
@@ -339,7 +348,7 @@ k_pencil_bf(PencilArgs a, int vpart_stride, int KPV) {
           }
       }
     }
-    __syncthreads();
+    lds_barrier_bf();
 #pragma unroll
     for (int j = 0; j < SPW; ++j)
 #pragma unroll
@@ -360,7 +369,7 @@ k_pencil_bf(PencilArgs a, int vpart_stride, int KPV) {
           }
       }
     }
-    __syncthreads();
+    lds_barrier_bf();
   }
 }
 
@@ -380,7 +389,7 @@ k_slice_inv_bf(AccArgs a, int vpart_stride, int KPV) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
   for (int i = tid; i < SPL * PLANE; i += nthr) S[i] = (__bf16)0.f;
-  __syncthreads();
+  lds_barrier_bf();
   const int nk32 = (max(a.n1, a.n2) + 31) / 32;
   const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
   const int c0 = 16 * SPW * w;
@@ -420,7 +429,7 @@ k_slice_inv_bf(AccArgs a, int vpart_stride, int KPV) {
           }
         }
       }
-      __syncthreads();
+      lds_barrier_bf();
       f4_t acc[SPW][NT];
 #pragma unroll
       for (int j = 0; j < SPW; ++j)
@@ -429,7 +438,7 @@ k_slice_inv_bf(AccArgs a, int vpart_stride, int KPV) {
       if (c0 < G::P)
         strip_gemm_bf<SPL, SPW, NT, LD, PLANE, true>(acc, S, (const __bf16*)a.V1, vpart_stride,
                                                      KPV, c0, nk32, lr, lg);
-      __syncthreads();
+      lds_barrier_bf();
       if (c0 < G::P) {
 #pragma unroll
         for (int j = 0; j < SPW; ++j)
@@ -441,7 +450,7 @@ k_slice_inv_bf(AccArgs a, int vpart_stride, int KPV) {
               if (irow < G::P) put<SPL, LD, PLANE>(S, irow, 16 * t + lr, acc[j][t][r]);
             }
       }
-      __syncthreads();
+      lds_barrier_bf();
 #pragma unroll
       for (int j = 0; j < SPW; ++j)
 #pragma unroll
@@ -482,7 +491,7 @@ k_slice_inv_bf(AccArgs a, int vpart_stride, int KPV) {
           }
         }
       }
-      __syncthreads();
+      lds_barrier_bf();
     }
     if (ACC) {
       double* vx = a.vx + (int64_t)u * a.ld_vx + soff;

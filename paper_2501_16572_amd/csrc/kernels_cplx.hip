@@ -20,6 +20,15 @@
 #include "launch.h"
 
 namespace kx {
+
+// Block barrier for LDS hand-offs only: waits for this wave's LDS operations
+// and meets the other waves, but leaves global loads in flight (a full
+// __syncthreads() also waits for them, which would serialize the prefetch of
+// the next work unit with the current one's MFMA work).  Nothing in these
+// kernels communicates through global memory within a block.
+__device__ __forceinline__ void lds_barrier_c() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 namespace {
 
 template <typename T>
@@ -135,13 +144,13 @@ __device__ __forceinline__ double cblock_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) red[w] = v;
-  __syncthreads();
+  lds_barrier_c();
   double s = 0.0;
   if (threadIdx.x == 0) {
     const int nw = blockDim.x >> 6;
     for (int i = 0; i < nw; ++i) s += red[i];
   }
-  __syncthreads();
+  lds_barrier_c();
   return s;
 }
 
@@ -162,7 +171,7 @@ k_slice_fwd_c(SliceArgs a) {
   const int PP = a.P * a.P;
   const int nk = (max(a.n1, a.n2) + 3) / 4;
   for (int i = tid; i < P * LD; i += nthr) Sr[i] = Si[i] = T(0);
-  __syncthreads();
+  lds_barrier_c();
   const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
   const int64_t nitems = (int64_t)a.npairs * a.n3;
   for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
@@ -178,12 +187,12 @@ k_slice_fwd_c(SliceArgs a) {
       pa = (const C2<T>*)a.src + (int64_t)p * a.ld_src + soff;
     }
     cstage<T, EPT, LD>(Sr, Si, pa, pb, a.n1, a.n12, m1, tid, nthr);
-    __syncthreads();
+    lds_barrier_c();
     acc_t ar[NT], ai[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) ar[t] = ai[t] = M::zero();
     cstrip<T, NT, LD, true, true>(ar, ai, Sr, Si, V1, V1 + PP, a.P, 16 * w, nk, lr, lg);
-    __syncthreads();
+    lds_barrier_c();
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -192,7 +201,7 @@ k_slice_fwd_c(SliceArgs a) {
         Sr[idx] = ar[t][r];
         Si[idx] = ai[t][r];
       }
-    __syncthreads();
+    lds_barrier_c();
 #pragma unroll
     for (int t = 0; t < NT; ++t) ar[t] = ai[t] = M::zero();
     cstrip<T, NT, LD, false, true>(ar, ai, Sr, Si, V2, V2 + PP, a.P, 16 * w, nk, lr, lg);
@@ -207,7 +216,7 @@ k_slice_fwd_c(SliceArgs a) {
           if (ai_ < a.n1) out[b * a.n1 + ai_] = C2<T>{ar[t][r], ai[t][r]};
         }
     }
-    __syncthreads();
+    lds_barrier_c();
   }
 }
 
@@ -242,7 +251,7 @@ k_pencil_c(PencilArgs a) {
         fr[qt][r] = (q < a.n12 && c < a.n3) ? a.ftab[q + (int64_t)a.n12 * c] : 0.0;
       }
   }
-  __syncthreads();
+  lds_barrier_c();
   constexpr int EPT = Q * P / CTiles<NK>::THREADS;
   for (int p = blockIdx.x / a.nchunks; p < a.npairs; p += pstep) {
     C2<T>* base = (C2<T>*)a.T + (int64_t)p * a.ld;
@@ -264,7 +273,7 @@ k_pencil_c(PencilArgs a) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier_c();
     acc_t ar[QT], ai[QT];
 #pragma unroll
     for (int t = 0; t < QT; ++t) ar[t] = ai[t] = M::zero();
@@ -276,7 +285,7 @@ k_pencil_c(PencilArgs a) {
         ar[t][r] = (T)((double)ar[t][r] * fr[t][r]);
         ai[t][r] = (T)((double)ai[t][r] * fr[t][r]);
       }
-    __syncthreads();
+    lds_barrier_c();
 #pragma unroll
     for (int t = 0; t < QT; ++t)
 #pragma unroll
@@ -285,7 +294,7 @@ k_pencil_c(PencilArgs a) {
         Sr[idx] = ar[t][r];
         Si[idx] = ai[t][r];
       }
-    __syncthreads();
+    lds_barrier_c();
 #pragma unroll
     for (int t = 0; t < QT; ++t) ar[t] = ai[t] = M::zero();
     cstrip<T, QT, LDQ, false, false>(ar, ai, Sr, Si, V3T, V3T + PP, a.P3, 16 * w, nk, lr, lg);
@@ -299,7 +308,7 @@ k_pencil_c(PencilArgs a) {
           if (q < a.n12) base[q + (int64_t)a.n12 * i] = C2<T>{ar[t][r], ai[t][r]};
         }
     }
-    __syncthreads();
+    lds_barrier_c();
   }
 }
 
@@ -322,7 +331,7 @@ k_slice_inv_c(AccArgs a) {
   const int PP = a.P * a.P;
   const int nk = (max(a.n1, a.n2) + 3) / 4;
   for (int i = tid; i < P * LD; i += nthr) Sr[i] = Si[i] = T(0);
-  __syncthreads();
+  lds_barrier_c();
   const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
   const int n_inner = ACC ? a.n_occ : 1;
   const int64_t nitems = (int64_t)(ACC ? a.n_t : a.n_t * a.n_occ) * a.n3;
@@ -340,12 +349,12 @@ k_slice_inv_c(AccArgs a) {
       const int p = ACC ? u * a.n_occ + mi : u;
       cstage<T, EPT, LD>(Sr, Si, (const C2<T>*)a.T + (int64_t)p * a.ld_T + soff, nullptr, a.n1,
                          a.n12, m1, tid, nthr);
-      __syncthreads();
+      lds_barrier_c();
       acc_t ar[NT], ai[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) ar[t] = ai[t] = M::zero();
       cstrip<T, NT, LD, true, false>(ar, ai, Sr, Si, V1T, V1T + PP, a.P, 16 * w, nk, lr, lg);
-      __syncthreads();
+      lds_barrier_c();
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -354,7 +363,7 @@ k_slice_inv_c(AccArgs a) {
           Sr[idx] = ar[t][r];
           Si[idx] = ai[t][r];
         }
-      __syncthreads();
+      lds_barrier_c();
 #pragma unroll
       for (int t = 0; t < NT; ++t) ar[t] = ai[t] = M::zero();
       cstrip<T, NT, LD, false, false>(ar, ai, Sr, Si, V2T, V2T + PP, a.P, 16 * w, nk, lr, lg);
@@ -386,7 +395,7 @@ k_slice_inv_c(AccArgs a) {
             if (ai_ < a.n1) out[b * a.n1 + ai_] = C2<T>{ar[t][r], ai[t][r]};
           }
       }
-      __syncthreads();
+      lds_barrier_c();
     }
     if (ACC) {
       const int b = 16 * w + lr;
