@@ -44,7 +44,7 @@ def pass_flops(n, npairs):
             "exx_fused_passC": 2.0 * N * (n1 + n2) * npairs}
 
 
-def run_form(kx, torch, cfg, psi_d, g_d, prec, path, steps, warmup, n_occ):
+def run_form(kx, torch, cfg, psi_d, g_d, prec, path, steps, warmup, n_occ, autotune=True):
     """Time `steps` exx_apply calls; returns timing, per-kernel trace and the
     result of one clean call."""
     plan = kx.kron_setup(cfg["n"], cfg["h"], cfg["bc"], cfg["order"], cfg["omega"], prec=prec)
@@ -54,6 +54,9 @@ def run_form(kx, torch, cfg, psi_d, g_d, prec, path, steps, warmup, n_occ):
         occ = g_d[:n_occ].contiguous()
         vx = torch.zeros(psi.shape, dtype=torch.float64, device="cuda")
         ex = torch.zeros(1, dtype=torch.float64, device="cuda")
+        tuning = None
+        if path == "fused" and autotune:
+            tuning = kx.kx_autotune(plan, psi[:n_occ], occ, psi)
         kx.exx_apply(plan, psi[:n_occ], occ, psi, vx, ex=ex, gphi=g_d, path=path)
         torch.cuda.synchronize()
         result = (vx.clone(), float(ex.item()))
@@ -78,7 +81,7 @@ def run_form(kx, torch, cfg, psi_d, g_d, prec, path, steps, warmup, n_occ):
         nt = plan.info()[7]
     finally:
         plan.destroy()
-    return dict(ms=ms, wall=wall, trace=trace, result=result, batch_targets=nt)
+    return dict(ms=ms, wall=wall, trace=trace, result=result, batch_targets=nt, tuning=tuning)
 
 
 def cpu_baseline(cfg, psi, g, n_occ, bands):
@@ -107,6 +110,8 @@ def main():
                     help="comma list of prec:path; the first one gives `value`")
     ap.add_argument("--cpu-bands", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch configuration instead of kx_autotune's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB on the device first: a kernel of known traffic for scaling "
                          "FETCH_SIZE / WRITE_SIZE counters")
@@ -148,12 +153,13 @@ def main():
     head = None
     for prec, path in forms:
         log("timing", prec, path)
-        r = run_form(kx, torch, cfg, psi_d, g_d, prec, path, args.steps, args.warmup, n_occ)
+        r = run_form(kx, torch, cfg, psi_d, g_d, prec, path, args.steps, args.warmup, n_occ,
+                     autotune=not args.no_autotune)
         t = r["ms"] / 1e3
         sps = solves * args.steps / t
         form = dict(solves_per_s=sps, ms_per_step=r["ms"] / args.steps,
                     useful_tflops=flops_per_solve * solves * args.steps / t / 1e12,
-                    batch_targets=r["batch_targets"],
+                    batch_targets=r["batch_targets"], tuning=r["tuning"],
                     kernels_ms={k: round(v[0] / args.steps, 4) for k, v in r["trace"].items()})
         vx, ex = r["result"]
         if ref_vx is None:

@@ -213,6 +213,28 @@ kx_status kx_trace_enable(int on);
 kx_status kx_trace_read(double* ms, int64_t* count, int nkinds);
 const char* kx_trace_name(int kind);
 
+/* kx_autotune -- choose the launch configuration of the three fused passes
+ * for this plan and workload (the batch Kronecker solve's analogue of the
+ * batch size n_c, Sec. II.B): for each candidate (occupancy variant x
+ * resident blocks per CU) it runs passes A, B, C on a sample batch of up to
+ * 8 target columns of the given data, times every pass with HIP events, and
+ * keeps the fastest candidate per pass in the plan (later exx_apply calls on
+ * any stream use it).  Arguments as exx_apply; nothing the caller owns is
+ * written (a private Vx buffer receives the sample's results).  Synchronous.
+ * If the environment variable KX_TUNE_CACHE names a file, choices are read
+ * from and appended to it (one line per key: arch, grid, precision, complex
+ * flag, n_occ), and a cached key skips the timing.  The occupancy variant
+ * exists for real FP64/FP32 plans; complex and split-BF16 plans tune the
+ * resident blocks per CU only. */
+kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, const double* d_occ,
+                      const void* d_phi, int64_t ld_phi, int n_b, void* stream);
+
+/* kx_plan_tuning -- the plan's current launch configuration per fused pass:
+ * out[2*i] = occupancy variant (0/1), out[2*i+1] = resident blocks per CU
+ * (0 = as many as fit), for passes i = A, B, C; out[6] = 1 if it came from
+ * kx_autotune (timed or cached). */
+kx_status kx_plan_tuning(kx_plan p, int out[7]);
+
 /* kx_last_error -- text for this thread's last non-OK status ("" if none).
  * The pointer stays valid until the next call on this thread. */
 const char* kx_last_error(void);

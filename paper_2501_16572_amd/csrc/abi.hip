@@ -185,6 +185,11 @@ struct kx_plan_s {
   int last_nt = 0;
   int max_blocks = 0;    // 0: as many as are co-resident
   unsigned ws_gen = 0;   // bumped whenever a device buffer is reallocated
+  // launch configuration per fused pass (A, B, C): occupancy variant and
+  // resident blocks per CU (0 = all that fit); set by kx_autotune
+  int tune_tv[3] = {0, 0, 0};
+  int tune_bpc[3] = {0, 0, 0};
+  bool tuned = false;
 };
 
 namespace {
@@ -263,38 +268,51 @@ kx_status check_exx_args(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, 
 bool is_bf(const kx_plan p) { return p->prec == KX_PREC_BF16X3 || p->prec == KX_PREC_BF16X6; }
 int bf_spl(const kx_plan p) { return p->prec == KX_PREC_BF16X3 ? 2 : 3; }
 
+int tuned_blocks(const kx_plan p, int pass) {
+  return p->tune_bpc[pass] > 0 ? p->tune_bpc[pass] * kx::device_cu_count() : p->max_blocks;
+}
+int tuned_variant(const kx_plan p, int pass, int variant) {
+  const bool real_mfma = !p->cplx && (p->prec == KX_PREC_FP64 || p->prec == KX_PREC_FP32);
+  return (real_mfma && p->tune_tv[pass]) ? (variant | kx::TUNE_ALT) : variant;
+}
+
 hipError_t launch_pass_a(kx_plan p, int variant, const kx::SliceArgs& A, int64_t items, hipStream_t s) {
   using namespace kx;
-  if (p->cplx) return launch_slice_fwd_c(p->prec == KX_PREC_FP64, p->nk12, variant, A, items, p->max_blocks, s);
-  if (p->prec == KX_PREC_FP64) return launch_slice_fwd_f64(p->nk12, variant, A, items, p->max_blocks, s);
-  if (p->prec == KX_PREC_FP32) return launch_slice_fwd_f32(p->nk12, variant, A, items, p->max_blocks, s);
+  const int mb = tuned_blocks(p, 0);
+  if (p->cplx) return launch_slice_fwd_c(p->prec == KX_PREC_FP64, p->nk12, variant, A, items, mb, s);
+  if (variant == SF_PAIR12) variant = tuned_variant(p, 0, variant);
+  if (p->prec == KX_PREC_FP64) return launch_slice_fwd_f64(p->nk12, variant, A, items, mb, s);
+  if (p->prec == KX_PREC_FP32) return launch_slice_fwd_f32(p->nk12, variant, A, items, mb, s);
   SliceArgs Ab = A;
   Ab.V1 = p->dVbf[0][0];
   Ab.V2 = p->dVbf[1][0];
-  return launch_slice_fwd_bf(bf_spl(p), p->bf_nt12, variant, Ab, items, p->max_blocks, p->bf_vps12,
+  return launch_slice_fwd_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, Ab, items, mb, p->bf_vps12,
                              p->bf_kp12, s);
 }
 
 hipError_t launch_pass_b(kx_plan p, const kx::PencilArgs& B, hipStream_t s) {
   using namespace kx;
-  if (p->cplx) return launch_pencil_c(p->prec == KX_PREC_FP64, p->nk3, B, p->max_blocks, s);
-  if (p->prec == KX_PREC_FP64) return launch_pencil_f64(p->nk3, PC_FSI, B, p->max_blocks, s);
-  if (p->prec == KX_PREC_FP32) return launch_pencil_f32(p->nk3, PC_FSI, B, p->max_blocks, s);
+  const int mb = tuned_blocks(p, 1), v = tuned_variant(p, 1, PC_FSI);
+  if (p->cplx) return launch_pencil_c(p->prec == KX_PREC_FP64, p->nk3, B, mb, s);
+  if (p->prec == KX_PREC_FP64) return launch_pencil_f64(p->nk3, v, B, mb, s);
+  if (p->prec == KX_PREC_FP32) return launch_pencil_f32(p->nk3, v, B, mb, s);
   PencilArgs Bb = B;
   Bb.V3 = p->dVbf[2][0];
   Bb.V3T = p->dVbf[2][1];
-  return launch_pencil_bf(bf_spl(p), p->bf_nt3, Bb, p->max_blocks, p->bf_vps3, p->bf_kp3, s);
+  return launch_pencil_bf(bf_spl(p), p->bf_nt3, Bb, mb, p->bf_vps3, p->bf_kp3, s);
 }
 
 hipError_t launch_pass_c(kx_plan p, int variant, const kx::AccArgs& C, int64_t items, hipStream_t s) {
   using namespace kx;
-  if (p->cplx) return launch_slice_inv_c(p->prec == KX_PREC_FP64, p->nk12, variant, C, items, p->max_blocks, s);
-  if (p->prec == KX_PREC_FP64) return launch_slice_inv_f64(p->nk12, variant, C, items, p->max_blocks, s);
-  if (p->prec == KX_PREC_FP32) return launch_slice_inv_f32(p->nk12, variant, C, items, p->max_blocks, s);
+  const int mb = tuned_blocks(p, 2);
+  if (p->cplx) return launch_slice_inv_c(p->prec == KX_PREC_FP64, p->nk12, variant, C, items, mb, s);
+  if (variant == SI_ACC12) variant = tuned_variant(p, 2, variant);
+  if (p->prec == KX_PREC_FP64) return launch_slice_inv_f64(p->nk12, variant, C, items, mb, s);
+  if (p->prec == KX_PREC_FP32) return launch_slice_inv_f32(p->nk12, variant, C, items, mb, s);
   AccArgs Cb = C;
   Cb.V1 = p->dVbf[0][1];
   Cb.V2 = p->dVbf[1][1];
-  return launch_slice_inv_bf(bf_spl(p), p->bf_nt12, variant, Cb, items, p->max_blocks, p->bf_vps12,
+  return launch_slice_inv_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, Cb, items, mb, p->bf_vps12,
                              p->bf_kp12, s);
 }
 
@@ -749,6 +767,182 @@ kx_status exx_apply(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, con
   if (st != KX_OK) return st;
   return enqueue_exx(p, d_psi, ld_psi, n_occ, d_occ, d_phi, ld_phi, n_b, d_vx, ld_vx, d_ex, d_gphi,
                      path, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+// One fused batch (targets n0 .. n0+cur-1) with events ev[0..3] around the
+// three passes; buffers already sized.
+hipError_t timed_batch(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, const double* occ,
+                       const void* phi, int64_t ld_phi, int cur, double* vx, int64_t ld_vx,
+                       hipEvent_t* ev, hipStream_t s) {
+  using namespace kx;
+  const int npairs = cur * n_occ;
+  SliceArgs A{};
+  A.n1 = p->n[0]; A.n2 = p->n[1]; A.n3 = p->n[2]; A.n12 = p->n12; A.N = p->N;
+  A.npairs = npairs; A.n_occ = n_occ;
+  A.psi = psi; A.ld_psi = ld_psi; A.phi = phi; A.ld_phi = ld_phi;
+  A.dst = p->d_ws; A.ld_dst = p->N;
+  A.V1 = p->dVmat[0]; A.V2 = p->dVmat[1]; A.P = p->P12;
+  PencilArgs B{};
+  B.n1 = p->n[0]; B.n2 = p->n[1]; B.n3 = p->n[2]; B.n12 = p->n12;
+  B.npairs = npairs; B.nchunks = (p->n12 + 63) / 64;
+  B.T = p->d_ws; B.ld = p->N; B.V3 = p->dVmat[2]; B.V3T = p->dVmatT[2]; B.P3 = p->P3; B.ftab = p->d_f;
+  AccArgs C{};
+  C.n1 = p->n[0]; C.n2 = p->n[1]; C.n3 = p->n[2]; C.n12 = p->n12; C.N = p->N;
+  C.n_t = cur; C.n_occ = n_occ; C.T = p->d_ws; C.ld_T = p->N;
+  C.psi = psi; C.ld_psi = ld_psi; C.occ = occ; C.phi = phi; C.ld_phi = ld_phi;
+  C.vx = vx; C.ld_vx = ld_vx; C.partials = nullptr;
+  C.V1 = p->dVmatT[0]; C.V2 = p->dVmatT[1]; C.P = p->P12;
+  hipEventRecord(ev[0], s);
+  hipError_t e = launch_pass_a(p, SF_PAIR12, A, (int64_t)npairs * p->n[2], s);
+  hipEventRecord(ev[1], s);
+  if (e == hipSuccess) e = launch_pass_b(p, B, s);
+  hipEventRecord(ev[2], s);
+  if (e == hipSuccess) e = launch_pass_c(p, SI_ACC12, C, (int64_t)cur * p->n[2], s);
+  hipEventRecord(ev[3], s);
+  return e;
+}
+
+std::string tune_key(kx_plan p, int n_occ) {
+  hipDeviceProp_t prop;
+  char arch[64] = "unknown";
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+    std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c)
+      if (*c == ' ' || *c == ':') *c = '_';
+  }
+  int rt = 0;
+  (void)hipRuntimeGetVersion(&rt);
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s|hip%d|%dx%dx%d|prec%d|cplx%d|occ%d", arch, rt, p->n[0], p->n[1],
+                p->n[2], p->prec, p->cplx ? 1 : 0, n_occ);
+  return buf;
+}
+
+bool tune_cache_lookup(const std::string& key, int tv[3], int bpc[3]) {
+  const char* path = std::getenv("KX_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char k[256];
+  int a[6];
+  bool found = false;
+  while (std::fscanf(f, "%255s %d %d %d %d %d %d", k, &a[0], &a[1], &a[2], &a[3], &a[4], &a[5]) == 7) {
+    if (key == k) {
+      for (int i = 0; i < 3; ++i) {
+        tv[i] = a[2 * i];
+        bpc[i] = a[2 * i + 1];
+      }
+      found = true;  // the last matching line wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_store(const std::string& key, const int tv[3], const int bpc[3]) {
+  const char* path = std::getenv("KX_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), tv[0], bpc[0], tv[1], bpc[1], tv[2], bpc[2]);
+  std::fclose(f);
+}
+
+}  // namespace
+
+kx_status kx_plan_tuning(kx_plan p, int out[7]) {
+  if (!p || !out) return fail(KX_EINVAL, "kx_plan_tuning: NULL argument");
+  for (int i = 0; i < 3; ++i) {
+    out[2 * i] = p->tune_tv[i];
+    out[2 * i + 1] = p->tune_bpc[i];
+  }
+  out[6] = p->tuned ? 1 : 0;
+  return KX_OK;
+}
+
+kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, const double* d_occ,
+                      const void* d_phi, int64_t ld_phi, int n_b, void* stream) {
+  double* dummy_vx = reinterpret_cast<double*>(alignof(double) * 64);  // validated, never used
+  kx_status st = check_exx_args(p, d_psi, ld_psi, n_occ, d_occ, d_phi, ld_phi, n_b, dummy_vx, p ? p->N : 0,
+                                nullptr, nullptr, KX_PATH_FUSED);
+  if (st != KX_OK) return st;
+  if (n_occ == 0 || n_b == 0) return KX_OK;
+  const bool real_mfma = !p->cplx && (p->prec == KX_PREC_FP64 || p->prec == KX_PREC_FP32);
+  const std::string key = tune_key(p, n_occ);
+  int tv[3], bpc[3];
+  if (tune_cache_lookup(key, tv, bpc)) {
+    for (int i = 0; i < 3; ++i) {
+      p->tune_tv[i] = tv[i];
+      p->tune_bpc[i] = bpc[i];
+    }
+    p->tuned = true;
+    return KX_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int ns = std::min(n_b, 8);
+  st = prepare_exx(p, n_occ, ns, KX_PATH_FUSED);
+  if (st != KX_OK) return st;
+  const size_t per_t = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+  const int cur = (int)std::min<size_t>((size_t)ns, p->ws_bytes / per_t);
+  double* vx = nullptr;
+  if (hipMalloc((void**)&vx, (size_t)cur * p->N * sizeof(double) * (p->cplx ? 2 : 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(KX_ENOMEM, "kx_autotune: sample Vx buffer");
+  }
+  // candidates: (occupancy variant, resident blocks per CU; 0 = all that fit)
+  static const int cand[][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {0, 4},
+                                {1, 0}, {1, 1}, {1, 2}, {1, 3}, {1, 4}};
+  const int ncand = real_mfma ? 10 : 5;  // the occupancy variant exists for FP64/FP32 real kernels
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) hipEventCreate(&ev[i]);
+  float best[3] = {1e30f, 1e30f, 1e30f};
+  int best_c[3] = {0, 0, 0};
+  hipError_t e = hipSuccess;
+  const int save_tv[3] = {p->tune_tv[0], p->tune_tv[1], p->tune_tv[2]};
+  const int save_bpc[3] = {p->tune_bpc[0], p->tune_bpc[1], p->tune_bpc[2]};
+  for (int c = 0; c < ncand && e == hipSuccess; ++c) {
+    for (int i = 0; i < 3; ++i) {
+      p->tune_tv[i] = cand[c][0];
+      p->tune_bpc[i] = cand[c][1];
+    }
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first run warms up
+      e = timed_batch(p, d_psi, ld_psi, n_occ, d_occ, d_phi, ld_phi, cur, vx, p->N, ev, s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+      if (e == hipSuccess && rep == 1) {
+        for (int i = 0; i < 3; ++i) {
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+          if (ms < best[i]) {
+            best[i] = ms;
+            best_c[i] = c;
+          }
+        }
+      }
+    }
+  }
+  for (int i = 0; i < 4; ++i) hipEventDestroy(ev[i]);
+  hipFree(vx);
+  if (e != hipSuccess) {
+    for (int i = 0; i < 3; ++i) {
+      p->tune_tv[i] = save_tv[i];
+      p->tune_bpc[i] = save_bpc[i];
+    }
+    return dev_fail(e, "kx_autotune");
+  }
+  for (int i = 0; i < 3; ++i) {
+    p->tune_tv[i] = cand[best_c[i]][0];
+    p->tune_bpc[i] = cand[best_c[i]][1];
+    tv[i] = p->tune_tv[i];
+    bpc[i] = p->tune_bpc[i];
+  }
+  p->tuned = true;
+  tune_cache_store(key, tv, bpc);
+  return KX_OK;
 }
 
 kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {

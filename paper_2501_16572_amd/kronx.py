@@ -32,7 +32,8 @@ FLAG_COMPLEX = 16
 # Every symbol declared in include/kronx.h.
 EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_batched",
            "kx_plan_info", "kx_plan_tables", "kx_host_eig1d", "kx_host_fd_weights",
-           "kx_last_error", "kx_trace_enable", "kx_trace_read", "kx_trace_name"]
+           "kx_last_error", "kx_trace_enable", "kx_trace_read", "kx_trace_name", "kx_autotune",
+           "kx_plan_tuning"]
 
 
 class KronxError(RuntimeError):
@@ -79,6 +80,8 @@ def load_library(path=None):
     lib.kx_trace_read.argtypes = [dp, i64p, ci]
     lib.kx_trace_name.argtypes = [ci]
     lib.kx_trace_name.restype = ctypes.c_char_p
+    lib.kx_autotune.argtypes = [vp, vp, i64, ci, vp, vp, i64, ci, vp]
+    lib.kx_plan_tuning.argtypes = [vp, ip]
     for name in EXPORTS:
         if name not in ("kx_last_error", "kx_trace_name"):
             getattr(lib, name).restype = ci
@@ -149,6 +152,13 @@ class Plan:
                "kx_plan_tables")
         return lam, (vr + 1j * vi if self.complex else vr)
 
+    def tuning(self):
+        """{pass: (occupancy variant, blocks per CU)} and whether it was autotuned."""
+        out = (ctypes.c_int * 7)()
+        _check(load_library().kx_plan_tuning(self.handle, out), "kx_plan_tuning")
+        return {"A": (out[0], out[1]), "B": (out[2], out[3]), "C": (out[4], out[5]),
+                "tuned": bool(out[6])}
+
     def destroy(self):
         if self.handle:
             _check(load_library().kron_destroy(self.handle), "kron_destroy")
@@ -211,6 +221,17 @@ def exx_apply(plan, psi, occ, phi, vx, ex=None, gphi=None, path="fused", stream=
         PATH[path], _stream(stream))
     _check(st, "exx_apply")
     return vx
+
+
+def kx_autotune(plan, psi, occ, phi, stream=None):
+    """Pick the fused passes' launch configuration on this workload (synchronous)."""
+    pp, ldp = _cols(psi, plan.N, "psi")
+    pf, ldf = _cols(phi, plan.N, "phi")
+    st = load_library().kx_autotune(plan.handle, ctypes.c_void_p(pp), ldp, psi.shape[0],
+                                    ctypes.c_void_p(occ.data_ptr()), ctypes.c_void_p(pf), ldf,
+                                    phi.shape[0], _stream(stream))
+    _check(st, "kx_autotune")
+    return plan.tuning()
 
 
 def exx_apply_batched(tasks, stream=None):

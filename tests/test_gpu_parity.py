@@ -407,3 +407,43 @@ def test_exx_kpoints(kx, prec):
 def vx_apply_kpoints_ref(psi, g, wk, solver_for):
     from oracle.exx import vx_apply_kpoints
     return vx_apply_kpoints(psi, g, wk, solver_for)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_choice_keeps_parity(kx, prec, tmp_path):
+    n, h = (40, 36, 44), (0.3, 0.3, 0.3)
+    say("autotune", prec)
+    psi = random_orbitals(n, h, 6, seed=70)
+    g = fermi_occupations(6, 5, 0.01, seed=70)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    psi_in = psi if prec == "fp64" else psi.astype(np.float32).astype(np.float64)
+    cache = tmp_path / "tune.txt"
+    old = os.environ.get("KX_TUNE_CACHE")
+    os.environ["KX_TUNE_CACHE"] = str(cache)
+    plans = []
+    try:
+        psid = to_dev(psi, dt)
+        occ = to_dev(g[:5], torch.float64)
+        for rep in range(2):  # second plan reads the cache
+            plan = kx.kron_setup(n, h, BCP, 12, 0.106, prec=prec)
+            plans.append(plan)
+            tun = kx.kx_autotune(plan, psid[:5], occ, psid)
+            assert tun["tuned"]
+            vx = torch.zeros((6, psid.shape[1]), dtype=torch.float64, device="cuda")
+            kx.exx_apply(plan, psid[:5], occ, psid, vx)
+            torch.cuda.synchronize()
+            W = to_host(vx)
+            if rep == 0:
+                first = tun
+        assert plans[1].tuning() == first
+        assert len(cache.read_text().strip().splitlines()) == 1
+    finally:
+        for p in plans:
+            p.destroy()
+        if old is None:
+            del os.environ["KX_TUNE_CACHE"]
+        else:
+            os.environ["KX_TUNE_CACHE"] = old
+    S = KronSolver(n, h, BCP, 12, 0.106)
+    Wref = vx_apply(psi_in[:5], g[:5], psi_in, S)
+    assert rel_fro(W, Wref) < (1e-12 if prec == "fp64" else 1e-6)
