@@ -216,11 +216,13 @@ const char* kx_trace_name(int kind);
 /* kx_autotune -- choose the launch configuration of the three fused passes
  * for this plan and workload (the batch Kronecker solve's analogue of the
  * batch size n_c, Sec. II.B): for each candidate (occupancy variant x
- * resident blocks per CU) it runs passes A, B, C on a sample batch of up to
- * 8 target columns of the given data, times every pass with HIP events, and
- * keeps the fastest candidate per pass in the plan (later exx_apply calls on
- * any stream use it).  Arguments as exx_apply; nothing the caller owns is
- * written (a private Vx buffer receives the sample's results).  Synchronous.
+ * resident blocks per CU) it runs passes A, B, C on the first batch that
+ * exx_apply would make of the given data (as many target columns as the
+ * workspace holds), times every pass with HIP events, and keeps the fastest
+ * candidate per pass in the plan (later exx_apply calls on any stream use
+ * it).  Arguments as exx_apply; nothing the caller owns is written (a private
+ * Vx buffer of one batch receives the results).  Synchronous; costs about
+ * twenty batches of device time once per key.
  * If the environment variable KX_TUNE_CACHE names a file, choices are read
  * from and appended to it (one line per key: arch, grid, precision, complex
  * flag, n_occ), and a cached key skips the timing.  The occupancy variant

@@ -884,7 +884,10 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
     return KX_OK;
   }
   hipStream_t s = (hipStream_t)stream;
-  const int ns = std::min(n_b, 8);
+  // Time the batch size a real call makes: the persistent grids fill the
+  // device differently on a smaller batch (pass C has one item per target
+  // slice), so a reduced sample picks configurations that lose at full size.
+  const int ns = n_b;
   st = prepare_exx(p, n_occ, ns, KX_PATH_FUSED);
   if (st != KX_OK) return st;
   const size_t per_t = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
