@@ -164,11 +164,25 @@ typedef struct {
 
 /* exx_apply_batched -- run ntasks exx_apply units (several k-point pairs and
  * several systems of uneven grid sizes) as one captured HIP graph on
- * `stream`.  The first call with a given task list captures the graph; later
- * calls with the same plans, pointers and sizes replay it.  Tasks writing the
- * same d_vx / d_ex are applied in task order.  All plans must share one
- * precision. */
+ * `stream` (the batched n_c-style scheduling of Sec. II.B over a whole task
+ * list).  Each task is cut into batches of targets as exx_apply does; the
+ * batches are scheduled in rounds, and in each round the batches of every
+ * pass whose plans share a kernel instantiation (element type, tile count,
+ * tuned launch configuration) run as ONE persistent launch that walks a task
+ * table; a lone batch launches as in exx_apply.  Two batches of one plan, or
+ * two batches with overlapping d_vx, never share a round, and overlapping
+ * outputs accumulate in task order.  The first call with a given task list
+ * captures the graph (and allocates its task tables); later calls with the
+ * same plans, pointers and sizes replay it.  All plans must share one
+ * precision.  Results are bitwise reproducible across replays. */
 kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream);
+
+/* kx_batched_schedule -- shape of the schedule that the last capture of
+ * exx_apply_batched in this process built: out[0] = rounds, out[1] = batches
+ * (one task contributes ceil(n_b / targets per batch)), out[2] = launches of
+ * the three fused passes, out[3] = the most batches that one launch ran.
+ * Host only; all zero before the first capture. */
+kx_status kx_batched_schedule(int out[4]);
 
 /* kx_plan_info -- sizes the plan chose (for reports and tests).
  *   out[0..2]  n1, n2, n3           out[3]  complex flag

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -154,7 +155,17 @@ struct kx_graph_entry {
   hipStream_t stream;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  void* d_tables;                     // task tables of the grouped launches (device)
 };
+
+void destroy_graph_entry(kx_graph_entry& g) {
+  if (g.exec) hipGraphExecDestroy(g.exec);
+  if (g.graph) hipGraphDestroy(g.graph);
+  if (g.d_tables) hipFree(g.d_tables);
+  g.exec = nullptr;
+  g.graph = nullptr;
+  g.d_tables = nullptr;
+}
 
 struct kx_plan_s {
   int n[3];
@@ -276,44 +287,124 @@ int tuned_variant(const kx_plan p, int pass, int variant) {
   return (real_mfma && p->tune_tv[pass]) ? (variant | kx::TUNE_ALT) : variant;
 }
 
-hipError_t launch_pass_a(kx_plan p, int variant, const kx::SliceArgs& A, int64_t items, hipStream_t s) {
+// The argument structs as the kernels of plan p read them: split-BF16 plans
+// take the split eigenvector parts in place of the FP64 matrices.
+kx::SliceArgs kernel_args_a(const kx_plan p, kx::SliceArgs A) {
+  if (is_bf(p) && !p->cplx) {
+    A.V1 = p->dVbf[0][0];
+    A.V2 = p->dVbf[1][0];
+  }
+  return A;
+}
+kx::PencilArgs kernel_args_b(const kx_plan p, kx::PencilArgs B) {
+  if (is_bf(p) && !p->cplx) {
+    B.V3 = p->dVbf[2][0];
+    B.V3T = p->dVbf[2][1];
+  }
+  return B;
+}
+kx::AccArgs kernel_args_c(const kx_plan p, kx::AccArgs C) {
+  if (is_bf(p) && !p->cplx) {
+    C.V1 = p->dVbf[0][1];
+    C.V2 = p->dVbf[1][1];
+  }
+  return C;
+}
+
+// The three fused passes for plan p.  With a task table (tt.ntasks > 0) the
+// launch runs every entry of the table (all of them batches of plans with
+// p's kernel instantiation, see launch_key) and `items` is the table's total.
+hipError_t launch_pass_a(kx_plan p, int variant, const kx::SliceArgs& A0, int64_t items, hipStream_t s,
+                         const kx::TaskTab& tt = kx::kNoTasks) {
   using namespace kx;
   const int mb = tuned_blocks(p, 0);
-  if (p->cplx) return launch_slice_fwd_c(p->prec == KX_PREC_FP64, p->nk12, variant, A, items, mb, s);
+  const SliceArgs A = kernel_args_a(p, A0);
+  if (p->cplx) return launch_slice_fwd_c(p->prec == KX_PREC_FP64, p->nk12, variant, A, items, mb, s, tt);
   if (variant == SF_PAIR12) variant = tuned_variant(p, 0, variant);
-  if (p->prec == KX_PREC_FP64) return launch_slice_fwd_f64(p->nk12, variant, A, items, mb, s);
-  if (p->prec == KX_PREC_FP32) return launch_slice_fwd_f32(p->nk12, variant, A, items, mb, s);
-  SliceArgs Ab = A;
-  Ab.V1 = p->dVbf[0][0];
-  Ab.V2 = p->dVbf[1][0];
-  return launch_slice_fwd_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, Ab, items, mb, p->bf_vps12,
-                             p->bf_kp12, s);
+  if (p->prec == KX_PREC_FP64) return launch_slice_fwd_f64(p->nk12, variant, A, items, mb, s, tt);
+  if (p->prec == KX_PREC_FP32) return launch_slice_fwd_f32(p->nk12, variant, A, items, mb, s, tt);
+  return launch_slice_fwd_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, A, items, mb, p->bf_vps12,
+                             p->bf_kp12, s, tt);
 }
 
-hipError_t launch_pass_b(kx_plan p, const kx::PencilArgs& B, hipStream_t s) {
+hipError_t launch_pass_b(kx_plan p, const kx::PencilArgs& B0, hipStream_t s,
+                         const kx::TaskTab& tt = kx::kNoTasks, int64_t items = 0) {
   using namespace kx;
   const int mb = tuned_blocks(p, 1), v = tuned_variant(p, 1, PC_FSI);
-  if (p->cplx) return launch_pencil_c(p->prec == KX_PREC_FP64, p->nk3, B, mb, s);
-  if (p->prec == KX_PREC_FP64) return launch_pencil_f64(p->nk3, v, B, mb, s);
-  if (p->prec == KX_PREC_FP32) return launch_pencil_f32(p->nk3, v, B, mb, s);
-  PencilArgs Bb = B;
-  Bb.V3 = p->dVbf[2][0];
-  Bb.V3T = p->dVbf[2][1];
-  return launch_pencil_bf(bf_spl(p), p->bf_nt3, Bb, mb, p->bf_vps3, p->bf_kp3, s);
+  const PencilArgs B = kernel_args_b(p, B0);
+  if (p->cplx) return launch_pencil_c(p->prec == KX_PREC_FP64, p->nk3, B, mb, s, tt, items);
+  if (p->prec == KX_PREC_FP64) return launch_pencil_f64(p->nk3, v, B, mb, s, tt, items);
+  if (p->prec == KX_PREC_FP32) return launch_pencil_f32(p->nk3, v, B, mb, s, tt, items);
+  return launch_pencil_bf(bf_spl(p), p->bf_nt3, B, mb, p->bf_vps3, p->bf_kp3, s, tt, items);
 }
 
-hipError_t launch_pass_c(kx_plan p, int variant, const kx::AccArgs& C, int64_t items, hipStream_t s) {
+hipError_t launch_pass_c(kx_plan p, int variant, const kx::AccArgs& C0, int64_t items, hipStream_t s,
+                         const kx::TaskTab& tt = kx::kNoTasks) {
   using namespace kx;
   const int mb = tuned_blocks(p, 2);
-  if (p->cplx) return launch_slice_inv_c(p->prec == KX_PREC_FP64, p->nk12, variant, C, items, mb, s);
+  const AccArgs C = kernel_args_c(p, C0);
+  if (p->cplx) return launch_slice_inv_c(p->prec == KX_PREC_FP64, p->nk12, variant, C, items, mb, s, tt);
   if (variant == SI_ACC12) variant = tuned_variant(p, 2, variant);
-  if (p->prec == KX_PREC_FP64) return launch_slice_inv_f64(p->nk12, variant, C, items, mb, s);
-  if (p->prec == KX_PREC_FP32) return launch_slice_inv_f32(p->nk12, variant, C, items, mb, s);
-  AccArgs Cb = C;
-  Cb.V1 = p->dVbf[0][1];
-  Cb.V2 = p->dVbf[1][1];
-  return launch_slice_inv_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, Cb, items, mb, p->bf_vps12,
-                             p->bf_kp12, s);
+  if (p->prec == KX_PREC_FP64) return launch_slice_inv_f64(p->nk12, variant, C, items, mb, s, tt);
+  if (p->prec == KX_PREC_FP32) return launch_slice_inv_f32(p->nk12, variant, C, items, mb, s, tt);
+  return launch_slice_inv_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, C, items, mb, p->bf_vps12,
+                             p->bf_kp12, s, tt);
+}
+
+// Plans whose batches can share one launch of pass `pass` (0 = A, 1 = B,
+// 2 = C) have equal keys: same kernel family, element type, tile count and
+// tuned variant.
+std::array<int, 6> launch_key(const kx_plan p, int pass) {
+  const int fam = p->cplx ? 2 : (is_bf(p) ? 1 : 0);
+  const int tiles = fam == 1 ? (pass == 1 ? p->bf_nt3 : p->bf_nt12) : (pass == 1 ? p->nk3 : p->nk12);
+  const int vps = fam == 1 ? (pass == 1 ? p->bf_vps3 : p->bf_vps12) : 0;
+  return {fam, p->prec, tiles, tuned_variant(p, pass, 0), vps, tuned_blocks(p, pass)};
+}
+
+// Arguments of one batch (targets n0 .. n0+cur-1) of an exx_apply on plan p.
+struct BatchArgs {
+  kx::SliceArgs A;
+  kx::PencilArgs B;
+  kx::AccArgs C;
+};
+BatchArgs batch_args(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, const double* occ,
+                     const void* phi, int64_t ld_phi, double* vx, int64_t ld_vx, bool want_ex, int n0,
+                     int cur) {
+  const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);  // bytes per grid value
+  const size_t vxw = p->cplx ? 2 : 1;                          // doubles per Vx value
+  const int npairs = cur * n_occ;
+  const char* phi0 = (const char*)phi + (size_t)n0 * ld_phi * eb;
+  BatchArgs b{};
+  kx::SliceArgs& A = b.A;
+  A.n1 = p->n[0]; A.n2 = p->n[1]; A.n3 = p->n[2]; A.n12 = p->n12; A.N = p->N;
+  A.npairs = npairs; A.n_occ = n_occ;
+  A.psi = psi; A.ld_psi = ld_psi; A.phi = phi0; A.ld_phi = ld_phi;
+  A.src = p->d_ws; A.ld_src = p->N;
+  A.dst = p->d_ws; A.ld_dst = p->N;
+  A.V1 = p->dVmat[0]; A.V2 = p->dVmat[1]; A.P = p->P12;
+  kx::PencilArgs& B = b.B;
+  B.n1 = p->n[0]; B.n2 = p->n[1]; B.n3 = p->n[2]; B.n12 = p->n12;
+  B.npairs = npairs; B.nchunks = (p->n12 + 63) / 64;
+  B.T = p->d_ws; B.ld = p->N; B.V3 = p->dVmat[2]; B.V3T = p->dVmatT[2]; B.P3 = p->P3; B.ftab = p->d_f;
+  kx::AccArgs& C = b.C;
+  C.n1 = p->n[0]; C.n2 = p->n[1]; C.n3 = p->n[2]; C.n12 = p->n12; C.N = p->N;
+  C.n_t = cur; C.n_occ = n_occ;
+  C.T = p->d_ws; C.ld_T = p->N;
+  C.psi = psi; C.ld_psi = ld_psi; C.occ = occ;
+  C.phi = phi0; C.ld_phi = ld_phi;
+  C.vx = vx + (size_t)n0 * ld_vx * vxw; C.ld_vx = ld_vx;
+  C.partials = want_ex ? p->d_part : nullptr;
+  C.dst = p->d_ws; C.ld_dst = p->N;
+  C.V1 = p->dVmatT[0]; C.V2 = p->dVmatT[1]; C.P = p->P12;
+  return b;
+}
+
+// Targets per batch that the plan's buffers hold (prepare_exx sized them).
+int held_batch(const kx_plan p, int n_occ, int n_b) {
+  const size_t per_t_ws = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+  const size_t per_t_part = std::max<size_t>(64, (size_t)p->n[2]) * sizeof(double);
+  const size_t cap = std::min(p->ws_bytes / per_t_ws, p->part_bytes / per_t_part);
+  return (int)std::min<size_t>(cap, (size_t)n_b);
 }
 
 // Enqueue one exx_apply.  Arguments already validated; buffers allocated for
@@ -343,40 +434,16 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
                       double* ex, const double* gphi, int path, hipStream_t s) {
   using namespace kx;
   if (n_occ == 0 || n_b == 0) return KX_OK;
-  // Batch size from the buffers actually held (prepare_exx sized them).
-  const size_t per_t_ws = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
-  const size_t per_t_part = std::max<size_t>(64, (size_t)p->n[2]) * sizeof(double);
-  size_t cap = std::min(p->ws_bytes / per_t_ws, p->part_bytes / per_t_part);
-  const int nt = (int)std::min<size_t>(cap, (size_t)n_b);
+  const int nt = held_batch(p, n_occ, n_b);
   if (nt < 1) return fail(KX_ESTATE, "exx_apply: workspace not prepared");
   p->last_nt = nt;
-  const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);  // bytes per grid value
-  const size_t vxw = p->cplx ? 2 : 1;                          // doubles per Vx value
   for (int n0 = 0; n0 < n_b; n0 += nt) {
     const int cur = std::min(nt, n_b - n0);
     const int npairs = cur * n_occ;
-    const char* phi0 = (const char*)phi + (size_t)n0 * ld_phi * eb;
-    SliceArgs A{};
-    A.n1 = p->n[0]; A.n2 = p->n[1]; A.n3 = p->n[2]; A.n12 = p->n12; A.N = p->N;
-    A.npairs = npairs; A.n_occ = n_occ;
-    A.psi = psi; A.ld_psi = ld_psi; A.phi = phi0; A.ld_phi = ld_phi;
-    A.src = p->d_ws; A.ld_src = p->N;
-    A.dst = p->d_ws; A.ld_dst = p->N;
-    A.V1 = p->dVmat[0]; A.V2 = p->dVmat[1]; A.P = p->P12;
-    PencilArgs B{};
-    B.n1 = p->n[0]; B.n2 = p->n[1]; B.n3 = p->n[2]; B.n12 = p->n12;
-    B.npairs = npairs; B.nchunks = (p->n12 + 63) / 64;
-    B.T = p->d_ws; B.ld = p->N; B.V3 = p->dVmat[2]; B.V3T = p->dVmatT[2]; B.P3 = p->P3; B.ftab = p->d_f;
-    AccArgs C{};
-    C.n1 = p->n[0]; C.n2 = p->n[1]; C.n3 = p->n[2]; C.n12 = p->n12; C.N = p->N;
-    C.n_t = cur; C.n_occ = n_occ;
-    C.T = p->d_ws; C.ld_T = p->N;
-    C.psi = psi; C.ld_psi = ld_psi; C.occ = occ;
-    C.phi = phi0; C.ld_phi = ld_phi;
-    C.vx = vx + (size_t)n0 * ld_vx * vxw; C.ld_vx = ld_vx;
-    C.partials = ex ? p->d_part : nullptr;
-    C.dst = p->d_ws; C.ld_dst = p->N;
-    C.V1 = p->dVmatT[0]; C.V2 = p->dVmatT[1]; C.P = p->P12;
+    const BatchArgs ba = batch_args(p, psi, ld_psi, n_occ, occ, phi, ld_phi, vx, ld_vx, ex != nullptr, n0, cur);
+    const kx::SliceArgs& A = ba.A;
+    const kx::PencilArgs& B = ba.B;
+    const kx::AccArgs& C = ba.C;
     const int64_t items_pairs = (int64_t)npairs * p->n[2];
     hipError_t e = hipSuccess;
     int per_target = p->n[2];
@@ -662,8 +729,7 @@ kx_status kron_destroy(kx_plan p) {
       bool uses = false;
       for (const kx_task& t : it->tasks) uses |= t.plan == p;
       if (uses) {
-        hipGraphExecDestroy(it->exec);
-        hipGraphDestroy(it->graph);
+        destroy_graph_entry(*it);
         it = g_graphs.erase(it);
       } else {
         ++it;
@@ -781,22 +847,10 @@ hipError_t timed_batch(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, co
                        hipEvent_t* ev, hipStream_t s) {
   using namespace kx;
   const int npairs = cur * n_occ;
-  SliceArgs A{};
-  A.n1 = p->n[0]; A.n2 = p->n[1]; A.n3 = p->n[2]; A.n12 = p->n12; A.N = p->N;
-  A.npairs = npairs; A.n_occ = n_occ;
-  A.psi = psi; A.ld_psi = ld_psi; A.phi = phi; A.ld_phi = ld_phi;
-  A.dst = p->d_ws; A.ld_dst = p->N;
-  A.V1 = p->dVmat[0]; A.V2 = p->dVmat[1]; A.P = p->P12;
-  PencilArgs B{};
-  B.n1 = p->n[0]; B.n2 = p->n[1]; B.n3 = p->n[2]; B.n12 = p->n12;
-  B.npairs = npairs; B.nchunks = (p->n12 + 63) / 64;
-  B.T = p->d_ws; B.ld = p->N; B.V3 = p->dVmat[2]; B.V3T = p->dVmatT[2]; B.P3 = p->P3; B.ftab = p->d_f;
-  AccArgs C{};
-  C.n1 = p->n[0]; C.n2 = p->n[1]; C.n3 = p->n[2]; C.n12 = p->n12; C.N = p->N;
-  C.n_t = cur; C.n_occ = n_occ; C.T = p->d_ws; C.ld_T = p->N;
-  C.psi = psi; C.ld_psi = ld_psi; C.occ = occ; C.phi = phi; C.ld_phi = ld_phi;
-  C.vx = vx; C.ld_vx = ld_vx; C.partials = nullptr;
-  C.V1 = p->dVmatT[0]; C.V2 = p->dVmatT[1]; C.P = p->P12;
+  const BatchArgs ba = batch_args(p, psi, ld_psi, n_occ, occ, phi, ld_phi, vx, ld_vx, false, 0, cur);
+  const SliceArgs& A = ba.A;
+  const PencilArgs& B = ba.B;
+  const AccArgs& C = ba.C;
   hipEventRecord(ev[0], s);
   hipError_t e = launch_pass_a(p, SF_PAIR12, A, (int64_t)npairs * p->n[2], s);
   hipEventRecord(ev[1], s);
@@ -948,6 +1002,66 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
   return KX_OK;
 }
 
+namespace {
+
+// One batch of one task of exx_apply_batched: targets n0 .. n0+cur-1.
+struct SubTask {
+  int task, n0, cur;
+};
+
+// Schedule of a task list: rounds of batches such that within a round no two
+// batches share a plan (they would share its workspace) or overlap in their
+// Vx output (batches of one launch update Vx concurrently).  A batch whose Vx
+// overlaps an earlier batch's goes to a later round, so overlapping outputs
+// accumulate in task order.  Greedy, in task order: each batch goes to the
+// first round that admits it.
+std::vector<std::vector<SubTask>> schedule_rounds(const kx_task* tasks, int ntasks) {
+  struct Placed {
+    SubTask st;
+    const kx_plan plan;
+    const double *lo, *hi;
+    size_t round;
+  };
+  std::vector<Placed> placed;
+  std::vector<std::vector<SubTask>> rounds;
+  for (int i = 0; i < ntasks; ++i) {
+    const kx_task& t = tasks[i];
+    if (t.n_occ == 0 || t.n_b == 0) continue;
+    const int nt = held_batch(t.plan, t.n_occ, t.n_b);
+    const size_t vxw = t.plan->cplx ? 2 : 1;
+    for (int n0 = 0; n0 < t.n_b; n0 += nt) {
+      const SubTask st{i, n0, std::min(nt, t.n_b - n0)};
+      const double* lo = t.d_vx + (size_t)n0 * t.ld_vx * vxw;
+      const double* hi = lo + (size_t)(st.cur - 1) * t.ld_vx * vxw + (size_t)t.plan->N * vxw;
+      size_t r = 0;
+      for (const Placed& q : placed)
+        if (lo < q.hi && q.lo < hi) r = std::max(r, q.round + 1);
+      for (;; ++r) {
+        bool ok = true;
+        for (const Placed& q : placed)
+          if (q.round == r && q.plan == t.plan) ok = false;
+        if (ok) break;
+      }
+      if (r >= rounds.size()) rounds.resize(r + 1);
+      rounds[r].push_back(st);
+      placed.push_back(Placed{st, t.plan, lo, hi, r});
+    }
+  }
+  return rounds;
+}
+
+// Shape of the last captured schedule (kx_batched_schedule).
+int g_last_sched[4] = {0, 0, 0, 0};
+
+// One launch of the grouped schedule: pass `pass` over the batches `subs`.
+struct GroupLaunch {
+  int pass;
+  std::vector<SubTask> subs;
+  size_t args_off = 0, pre_off = 0;  // byte offsets of its table in the device block
+};
+
+}  // namespace
+
 kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
   if (ntasks < 0 || (ntasks > 0 && !tasks)) return fail(KX_EINVAL, "exx_apply_batched: bad task list");
   if (ntasks == 0) return KX_OK;
@@ -974,8 +1088,7 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
       bool fresh = true;
       for (int i = 0; i < ntasks; ++i) fresh &= g.generations[i] == tasks[i].plan->ws_gen;
       if (!fresh) {  // a workspace moved since capture: capture again
-        hipGraphExecDestroy(g.exec);
-        hipGraphDestroy(g.graph);
+        destroy_graph_entry(g);
         g_graphs.erase(it);
         break;
       }
@@ -984,41 +1097,179 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
       return KX_OK;
     }
   }
+
+  // Schedule: per round, the batches of each pass are grouped by kernel
+  // instantiation; a group of several batches is one persistent launch over
+  // a task table, a single batch launches with its own arguments.
+  const std::vector<std::vector<SubTask>> rounds = schedule_rounds(tasks, ntasks);
+  std::vector<GroupLaunch> launches;
+  size_t tab_bytes = 0;
+  auto arg_size = [](int pass) {
+    return pass == 0 ? sizeof(kx::SliceArgs) : pass == 1 ? sizeof(kx::PencilArgs) : sizeof(kx::AccArgs);
+  };
+  for (const auto& round : rounds) {
+    for (int pass = 0; pass < 3; ++pass) {
+      std::vector<std::array<int, 6>> keys;
+      std::vector<std::vector<SubTask>> groups;
+      for (const SubTask& st : round) {
+        const std::array<int, 6> k = launch_key(tasks[st.task].plan, pass);
+        size_t gi = 0;
+        while (gi < keys.size() && keys[gi] != k) ++gi;
+        if (gi == keys.size()) {
+          keys.push_back(k);
+          groups.emplace_back();
+        }
+        groups[gi].push_back(st);
+      }
+      for (auto& g : groups) {
+        GroupLaunch gl;
+        gl.pass = pass;
+        gl.subs = g;
+        if (g.size() > 1) {
+          tab_bytes = (tab_bytes + 255) & ~(size_t)255;
+          gl.args_off = tab_bytes;
+          tab_bytes += g.size() * arg_size(pass);
+          tab_bytes = (tab_bytes + 7) & ~(size_t)7;
+          gl.pre_off = tab_bytes;
+          tab_bytes += (g.size() + 1) * sizeof(int64_t);
+        }
+        launches.push_back(std::move(gl));
+      }
+    }
+  }
+  {
+    int nsub = 0, widest = 0;
+    for (const auto& r : rounds) nsub += (int)r.size();
+    for (const GroupLaunch& gl : launches) widest = std::max(widest, (int)gl.subs.size());
+    g_last_sched[0] = (int)rounds.size();
+    g_last_sched[1] = nsub;
+    g_last_sched[2] = (int)launches.size();
+    g_last_sched[3] = widest;
+  }
+  void* d_tab = nullptr;
+  if (tab_bytes) {
+    std::vector<char> h(tab_bytes, 0);
+    for (const GroupLaunch& gl : launches) {
+      if (gl.subs.size() < 2) continue;
+      int64_t* pre = (int64_t*)(h.data() + gl.pre_off);
+      pre[0] = 0;
+      for (size_t j = 0; j < gl.subs.size(); ++j) {
+        const SubTask& st = gl.subs[j];
+        const kx_task& t = tasks[st.task];
+        const kx_plan p = t.plan;
+        const BatchArgs ba = batch_args(p, t.d_psi, t.ld_psi, t.n_occ, t.d_occ, t.d_phi, t.ld_phi, t.d_vx,
+                                        t.ld_vx, t.d_ex != nullptr, st.n0, st.cur);
+        int64_t items = 0;
+        char* dst = h.data() + gl.args_off + j * arg_size(gl.pass);
+        if (gl.pass == 0) {
+          const kx::SliceArgs a = kernel_args_a(p, ba.A);
+          std::memcpy(dst, &a, sizeof(a));
+          items = (int64_t)ba.A.npairs * p->n[2];
+        } else if (gl.pass == 1) {
+          const kx::PencilArgs b = kernel_args_b(p, ba.B);
+          std::memcpy(dst, &b, sizeof(b));
+          items = (int64_t)ba.B.nchunks * ba.B.npairs;
+        } else {
+          const kx::AccArgs c = kernel_args_c(p, ba.C);
+          std::memcpy(dst, &c, sizeof(c));
+          items = (int64_t)st.cur * p->n[2];
+        }
+        pre[j + 1] = pre[j] + items;
+      }
+    }
+    hipError_t e = hipMalloc(&d_tab, tab_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(KX_ENOMEM, "exx_apply_batched: task tables");
+    }
+    e = hipMemcpy(d_tab, h.data(), tab_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      hipFree(d_tab);
+      return dev_fail(e, "exx_apply_batched: task table upload");
+    }
+  }
+
   // Capture on a private stream (capture is not allowed on the legacy default
   // stream); the instantiated graph is launched on the caller's stream.
   hipGraph_t graph = nullptr;
   hipStream_t cap = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-  if (e != hipSuccess) return dev_fail(e, "exx_apply_batched capture stream");
-  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) hipStreamDestroy(cap);
+  }
   if (e != hipSuccess) {
-    hipStreamDestroy(cap);
+    if (d_tab) hipFree(d_tab);
     return dev_fail(e, "exx_apply_batched capture");
   }
-  kx_status st = KX_OK;
-  for (int i = 0; i < ntasks && st == KX_OK; ++i) {
-    const kx_task& t = tasks[i];
-    st = enqueue_exx(t.plan, t.d_psi, t.ld_psi, t.n_occ, t.d_occ, t.d_phi, t.ld_phi, t.n_b, t.d_vx,
-                     t.ld_vx, t.d_ex, t.d_gphi, KX_PATH_FUSED, cap);
+  size_t li = 0;
+  for (size_t r = 0; r < rounds.size() && e == hipSuccess; ++r) {
+    for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
+      for (; li < launches.size() && launches[li].pass == pass && e == hipSuccess; ++li) {
+        const GroupLaunch& gl = launches[li];
+        const SubTask& st0 = gl.subs[0];
+        const kx_task& t0 = tasks[st0.task];
+        const kx_plan p0 = t0.plan;
+        const BatchArgs ba = batch_args(p0, t0.d_psi, t0.ld_psi, t0.n_occ, t0.d_occ, t0.d_phi, t0.ld_phi,
+                                        t0.d_vx, t0.ld_vx, t0.d_ex != nullptr, st0.n0, st0.cur);
+        kx::TaskTab tt = kx::kNoTasks;
+        int64_t total = 0;
+        if (gl.subs.size() > 1) {
+          tt.args = (const char*)d_tab + gl.args_off;
+          tt.pre = (const int64_t*)((const char*)d_tab + gl.pre_off);
+          tt.ntasks = (int)gl.subs.size();
+          for (const SubTask& st : gl.subs) {
+            const kx_plan p = tasks[st.task].plan;
+            const int64_t np = (int64_t)st.cur * tasks[st.task].n_occ;
+            total += pass == 0 ? np * p->n[2] : pass == 1 ? (int64_t)((p->n12 + 63) / 64) * np
+                                                          : (int64_t)st.cur * p->n[2];
+          }
+        }
+        if (pass == 0) {
+          e = launch_pass_a(p0, kx::SF_PAIR12, ba.A, tt.ntasks ? total : (int64_t)ba.A.npairs * p0->n[2], cap, tt);
+        } else if (pass == 1) {
+          e = launch_pass_b(p0, ba.B, cap, tt, total);
+        } else {
+          e = launch_pass_c(p0, kx::SI_ACC12, ba.C, tt.ntasks ? total : (int64_t)st0.cur * p0->n[2], cap, tt);
+          // E_x of every batch of this launch
+          for (size_t j = 0; j < gl.subs.size() && e == hipSuccess; ++j) {
+            const SubTask& st = gl.subs[j];
+            const kx_task& t = tasks[st.task];
+            if (t.d_ex)
+              e = kx::launch_ex_finalize(t.plan->d_part, st.cur, t.plan->n[2], t.d_gphi + st.n0, t.plan->dV,
+                                         t.d_ex, cap);
+          }
+        }
+      }
+    }
   }
-  e = hipStreamEndCapture(cap, &graph);
+  hipError_t e2 = hipStreamEndCapture(cap, &graph);
   hipStreamDestroy(cap);
-  if (st != KX_OK) {
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) {
     if (graph) hipGraphDestroy(graph);
-    return st;
+    if (d_tab) hipFree(d_tab);
+    return dev_fail(e, "exx_apply_batched capture");
   }
-  if (e != hipSuccess) return dev_fail(e, "exx_apply_batched end capture");
   hipGraphExec_t exec = nullptr;
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     hipGraphDestroy(graph);
+    if (d_tab) hipFree(d_tab);
     return dev_fail(e, "exx_apply_batched instantiate");
   }
   std::vector<unsigned> gens(ntasks);
   for (int i = 0; i < ntasks; ++i) gens[i] = tasks[i].plan->ws_gen;
-  g_graphs.push_back(kx_graph_entry{std::vector<kx_task>(tasks, tasks + ntasks), gens, s, graph, exec});
+  g_graphs.push_back(kx_graph_entry{std::vector<kx_task>(tasks, tasks + ntasks), gens, s, graph, exec, d_tab});
   e = hipGraphLaunch(exec, s);
   if (e != hipSuccess) return dev_fail(e, "exx_apply_batched launch");
+  return KX_OK;
+}
+
+kx_status kx_batched_schedule(int out[4]) {
+  if (!out) return fail(KX_EINVAL, "kx_batched_schedule: NULL argument");
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  for (int i = 0; i < 4; ++i) out[i] = g_last_sched[i];
   return KX_OK;
 }
 

@@ -70,4 +70,36 @@ struct AccArgs {
   int P;
 };
 
+// Several batches in one persistent launch (the batched entry point): the
+// launch's flat item space is the concatenation of the entries' item spaces,
+// entry i owning items [pre[i], pre[i+1]); its arguments are args[i], an
+// array of the pass's argument struct in device memory.  ntasks = 0: one
+// batch, described by the kernel's own argument struct.
+struct TaskTab {
+  const void* args;
+  const int64_t* pre;
+  int ntasks;
+};
+
+// Entry of flat item g: its index, a copy of its argument struct, and the
+// item's index within it.  The table is read through the constant address
+// space (it does not change during a launch), so the loads are scalar and the
+// arguments stay in SGPRs as kernel arguments do.  A linear scan: a launch
+// holds a few dozen entries at most.
+template <typename A>
+__device__ __forceinline__ A task_args(const TaskTab& tt, int64_t g, int64_t& item, int& t) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef __attribute__((address_space(4))) const int64_t cpre_t;
+  typedef __attribute__((address_space(4))) const A cargs_t;
+#else  // the host pass only parses device functions
+  typedef const int64_t cpre_t;
+  typedef const A cargs_t;
+#endif
+  cpre_t* pre = (cpre_t*)tt.pre;
+  t = 0;
+  while (t + 1 < tt.ntasks && pre[t + 1] <= g) ++t;
+  item = g - pre[t];
+  return ((cargs_t*)tt.args)[t];
+}
+
 }  // namespace kx

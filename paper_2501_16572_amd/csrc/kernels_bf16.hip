@@ -167,9 +167,9 @@ struct BfWaves {
 // (V1^T S), mode-2 forward (S V2) per frontal slice.
 // V parts: a.V1 = split(V1^T) [a][k], a.V2 = split(V2^T) [b][k].
 // ---------------------------------------------------------------------------
-template <int SPL, int NT, int SPW, int IN>
+template <int SPL, int NT, int SPW, int IN, bool MT = false>
 __global__ void __launch_bounds__((BfWaves<NT, SPW>::THREADS))
-k_slice_fwd_bf(SliceArgs a, int vpart_stride, int KPV) {
+k_slice_fwd_bf(SliceArgs a0, int vpart_stride, int KPV, TaskTab tt) {
   using G = BfGeo<NT>;
   constexpr int LD = G::LD, PLANE = G::LINES * LD;
   constexpr int NW = BfWaves<NT, SPW>::W;
@@ -178,13 +178,19 @@ k_slice_fwd_bf(SliceArgs a, int vpart_stride, int KPV) {
   const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
   for (int i = tid; i < SPL * PLANE; i += nthr) S[i] = (__bf16)0.f;
   lds_barrier_bf();
-  const int nk32 = (max(a.n1, a.n2) + 31) / 32;
-  const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
   constexpr int EPT0 = (G::P * G::P + 64 * NW - 1) / (64 * NW);
   constexpr int CH = EPT0 < 16 ? EPT0 : 16;
   constexpr int EPT = (EPT0 + CH - 1) / CH * CH;
-  const int64_t nitems = (int64_t)a.npairs * a.n3;
-  for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+  const int64_t total = MT ? tt.pre[tt.ntasks] : (int64_t)a0.npairs * a0.n3;
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    int64_t item = g;
+    SliceArgs a = a0;
+    if constexpr (MT) {
+      int t;
+      a = task_args<SliceArgs>(tt, g, item, t);
+    }
+    const int nk32 = (max(a.n1, a.n2) + 31) / 32;
+    const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
     const int p = (int)(item / a.n3), i3 = (int)(item - (int64_t)p * a.n3);
     const int64_t soff = (int64_t)i3 * a.n12;
     float* out = (float*)a.dst + (int64_t)p * a.ld_dst + soff;
@@ -276,9 +282,9 @@ k_slice_fwd_bf(SliceArgs a, int vpart_stride, int KPV) {
 // (Z V3^T) on chunks of 64 pencils, in place.
 // V parts: a.V3 = split(V3^T) [c][k], a.V3T = split(V3) [i][c].
 // ---------------------------------------------------------------------------
-template <int SPL, int NT, int SPW>
+template <int SPL, int NT, int SPW, bool MT = false>
 __global__ void __launch_bounds__((BfWaves<NT, SPW>::THREADS))
-k_pencil_bf(PencilArgs a, int vpart_stride, int KPV) {
+k_pencil_bf(PencilArgs a0, int vpart_stride, int KPV, TaskTab tt) {
   using G = BfGeo<NT>;
   constexpr int QT = 4, Q = 64;
   constexpr int LD = G::LD, PLANE = Q * LD;
@@ -286,29 +292,27 @@ k_pencil_bf(PencilArgs a, int vpart_stride, int KPV) {
   __shared__ __attribute__((aligned(16))) __bf16 S[SPL * PLANE];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
-  const int chunk = blockIdx.x % a.nchunks;
-  const int pstep = gridDim.x / a.nchunks;
-  const int q0 = chunk * Q;
-  const int nk32 = (a.n3 + 31) / 32;
   const int c0 = 16 * SPW * w;
   for (int i = tid; i < SPL * PLANE; i += nthr) S[i] = (__bf16)0.f;
   double fr[SPW][QT][4];
+  auto load_f = [&](const PencilArgs& a, int q0) {
 #pragma unroll
-  for (int j = 0; j < SPW; ++j) {
-    const int c = c0 + 16 * j + lr;
+    for (int j = 0; j < SPW; ++j) {
+      const int c = c0 + 16 * j + lr;
 #pragma unroll
-    for (int qt = 0; qt < QT; ++qt)
+      for (int qt = 0; qt < QT; ++qt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = q0 + 16 * qt + 4 * lg + r;
-        fr[j][qt][r] = (q < a.n12 && c < a.n3) ? a.ftab[q + (int64_t)a.n12 * c] : 0.0;
-      }
-  }
-  lds_barrier_bf();
+        for (int r = 0; r < 4; ++r) {
+          const int q = q0 + 16 * qt + 4 * lg + r;
+          fr[j][qt][r] = (q < a.n12 && c < a.n3) ? a.ftab[q + (int64_t)a.n12 * c] : 0.0;
+        }
+    }
+  };
   constexpr int EPT0 = (Q * G::P + 64 * NW - 1) / (64 * NW);
   constexpr int CH = EPT0 < 16 ? EPT0 : 16;
   constexpr int EPT = (EPT0 + CH - 1) / CH * CH;
-  for (int p = blockIdx.x / a.nchunks; p < a.npairs; p += pstep) {
+  auto run = [&](const PencilArgs& a, int q0, int p) {
+    const int nk32 = (a.n3 + 31) / 32;
     float* base = (float*)a.T + (int64_t)p * a.ld;
     for (int j0 = 0; j0 < EPT; j0 += CH) {
       float v[CH];
@@ -370,6 +374,34 @@ k_pencil_bf(PencilArgs a, int vpart_stride, int KPV) {
       }
     }
     lds_barrier_bf();
+
+  };
+  if constexpr (!MT) {
+    const int chunk = blockIdx.x % a0.nchunks;
+    const int pstep = gridDim.x / a0.nchunks;
+    const int q0 = chunk * Q;
+    load_f(a0, q0);
+    lds_barrier_bf();
+    for (int p = blockIdx.x / a0.nchunks; p < a0.npairs; p += pstep) run(a0, q0, p);
+  } else {
+    // contiguous runs of (chunk, pair) items, the pair fastest (as the FP32/FP64 kernel)
+    lds_barrier_bf();
+    const int64_t total = tt.pre[tt.ntasks];
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * per, g1 = min(total, g0 + per);
+    int cur_t = -1, cur_c = -1;
+    for (int64_t g = g0; g < g1; ++g) {
+      int64_t item;
+      int t;
+      const PencilArgs a = task_args<PencilArgs>(tt, g, item, t);
+      const int chunk = (int)(item / a.npairs), p = (int)(item - (int64_t)chunk * a.npairs);
+      if (t != cur_t || chunk != cur_c) {
+        load_f(a, chunk * Q);
+        cur_t = t;
+        cur_c = chunk;
+      }
+      run(a, chunk * Q, p);
+    }
   }
 }
 
@@ -378,9 +410,9 @@ k_pencil_bf(PencilArgs a, int vpart_stride, int KPV) {
 // and FP64 accumulation into Vx with E_x partials, else store.
 // V parts: a.V1 = split(V1) [i][a], a.V2 = split(V2) [b][k].
 // ---------------------------------------------------------------------------
-template <int SPL, int NT, int SPW, bool ACC>
+template <int SPL, int NT, int SPW, bool ACC, bool MT = false>
 __global__ void __launch_bounds__((BfWaves<NT, SPW>::THREADS))
-k_slice_inv_bf(AccArgs a, int vpart_stride, int KPV) {
+k_slice_inv_bf(AccArgs a0, int vpart_stride, int KPV, TaskTab tt) {
   using G = BfGeo<NT>;
   constexpr int LD = G::LD, PLANE = G::LINES * LD;
   constexpr int NW = BfWaves<NT, SPW>::W;
@@ -390,15 +422,22 @@ k_slice_inv_bf(AccArgs a, int vpart_stride, int KPV) {
   const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
   for (int i = tid; i < SPL * PLANE; i += nthr) S[i] = (__bf16)0.f;
   lds_barrier_bf();
-  const int nk32 = (max(a.n1, a.n2) + 31) / 32;
-  const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
   const int c0 = 16 * SPW * w;
   constexpr int EPT0 = (G::P * G::P + 64 * NW - 1) / (64 * NW);
   constexpr int CH = EPT0 < 16 ? EPT0 : 16;
   constexpr int EPT = (EPT0 + CH - 1) / CH * CH;
-  const int n_inner = ACC ? a.n_occ : 1;
-  const int64_t nitems = (int64_t)(ACC ? a.n_t : a.n_t * a.n_occ) * a.n3;
-  for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+  const int64_t total =
+      MT ? tt.pre[tt.ntasks] : (int64_t)(ACC ? a0.n_t : a0.n_t * a0.n_occ) * a0.n3;
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    int64_t item = g;
+    AccArgs a = a0;
+    if constexpr (MT) {
+      int t;
+      a = task_args<AccArgs>(tt, g, item, t);
+    }
+    const int nk32 = (max(a.n1, a.n2) + 31) / 32;
+    const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
+    const int n_inner = ACC ? a.n_occ : 1;
     const int u = (int)(item / a.n3), i3 = (int)(item - (int64_t)u * a.n3);
     const int64_t soff = (int64_t)i3 * a.n12;
     double wacc[ACC ? SPW : 1][ACC ? NT : 1][4];
@@ -550,39 +589,47 @@ constexpr int spw_for() { return (NT >= 4 && NT % 2 == 0) ? 2 : 1; }
 
 template <int SPL, int NT>
 hipError_t fwd_nt(int variant, const SliceArgs& a, int64_t items, int max_blocks, int vps, int kpv,
-                  hipStream_t s) {
+                  hipStream_t s, const TaskTab& tt) {
   constexpr int SPW = spw_for<NT>();
   constexpr int TH = BfWaves<NT, SPW>::THREADS;
-  void (*k)(SliceArgs, int, int) = variant == SF_PAIR12 ? k_slice_fwd_bf<SPL, NT, SPW, 0>
-                                                        : k_slice_fwd_bf<SPL, NT, SPW, 1>;
+  void (*k)(SliceArgs, int, int, TaskTab) = tt.ntasks ? k_slice_fwd_bf<SPL, NT, SPW, 0, true>
+                                             : variant == SF_PAIR12 ? k_slice_fwd_bf<SPL, NT, SPW, 0>
+                                                                    : k_slice_fwd_bf<SPL, NT, SPW, 1>;
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k, dim3(bf_grid(k, TH, items, max_blocks)), dim3(TH), 0, s, a, vps, kpv);
+  hipLaunchKernelGGL(k, dim3(bf_grid(k, TH, items, max_blocks)), dim3(TH), 0, s, a, vps, kpv, tt);
   return hipGetLastError();
 }
 
 template <int SPL, int NT>
-hipError_t pencil_nt(const PencilArgs& a, int max_blocks, int vps, int kpv, hipStream_t s) {
+hipError_t pencil_nt(const PencilArgs& a, int max_blocks, int vps, int kpv, hipStream_t s,
+                     const TaskTab& tt, int64_t items) {
   constexpr int SPW = 1;  // the per-block f-table slice is kept per strip
   constexpr int TH = BfWaves<NT, SPW>::THREADS;
-  void (*k)(PencilArgs, int, int) = k_pencil_bf<SPL, NT, SPW>;
+  void (*k)(PencilArgs, int, int, TaskTab) = tt.ntasks ? k_pencil_bf<SPL, NT, SPW, true> : k_pencil_bf<SPL, NT, SPW>;
+  if (tt.ntasks) {
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k, dim3(bf_grid(k, TH, items, max_blocks)), dim3(TH), 0, s, a, vps, kpv, tt);
+    return hipGetLastError();
+  }
   if (a.npairs <= 0 || a.nchunks <= 0) return hipSuccess;
   int64_t cap = (int64_t)bf_resident(k, TH) * device_cu_count();
   if (max_blocks > 0) cap = std::min<int64_t>(cap, max_blocks);
   int64_t groups = std::max<int64_t>(1, cap / a.nchunks);
   groups = std::min<int64_t>(groups, a.npairs);
-  hipLaunchKernelGGL(k, dim3((unsigned)(groups * a.nchunks)), dim3(TH), 0, s, a, vps, kpv);
+  hipLaunchKernelGGL(k, dim3((unsigned)(groups * a.nchunks)), dim3(TH), 0, s, a, vps, kpv, tt);
   return hipGetLastError();
 }
 
 template <int SPL, int NT>
 hipError_t inv_nt(int variant, const AccArgs& a, int64_t items, int max_blocks, int vps, int kpv,
-                  hipStream_t s) {
+                  hipStream_t s, const TaskTab& tt) {
   constexpr int SPW = 1;  // the FP64 Vx accumulator is kept per strip
   constexpr int TH = BfWaves<NT, SPW>::THREADS;
-  void (*k)(AccArgs, int, int) = variant == SI_ACC12 ? k_slice_inv_bf<SPL, NT, SPW, true>
-                                                     : k_slice_inv_bf<SPL, NT, SPW, false>;
+  void (*k)(AccArgs, int, int, TaskTab) = tt.ntasks ? k_slice_inv_bf<SPL, NT, SPW, true, true>
+                                           : variant == SI_ACC12 ? k_slice_inv_bf<SPL, NT, SPW, true>
+                                                                 : k_slice_inv_bf<SPL, NT, SPW, false>;
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k, dim3(bf_grid(k, TH, items, max_blocks)), dim3(TH), 0, s, a, vps, kpv);
+  hipLaunchKernelGGL(k, dim3(bf_grid(k, TH, items, max_blocks)), dim3(TH), 0, s, a, vps, kpv, tt);
   return hipGetLastError();
 }
 
@@ -591,13 +638,13 @@ hipError_t inv_nt(int variant, const AccArgs& a, int64_t items, int max_blocks, 
 }  // namespace
 
 hipError_t launch_slice_fwd_bf(int spl, int nt, int variant, const SliceArgs& a, int64_t items,
-                               int max_blocks, int vps, int kpv, hipStream_t s) {
+                               int max_blocks, int vps, int kpv, hipStream_t s, const TaskTab& tt) {
   if (variant != SF_PAIR12 && variant != SF_LOAD12) return hipErrorInvalidValue;
   switch (nt) {
 #define C(n)                                                                        \
   case n:                                                                           \
-    return spl == 2 ? fwd_nt<2, n>(variant, a, items, max_blocks, vps, kpv, s)      \
-                    : fwd_nt<3, n>(variant, a, items, max_blocks, vps, kpv, s);
+    return spl == 2 ? fwd_nt<2, n>(variant, a, items, max_blocks, vps, kpv, s, tt)  \
+                    : fwd_nt<3, n>(variant, a, items, max_blocks, vps, kpv, s, tt);
     KX_NT_CASES(C)
 #undef C
     default: return hipErrorInvalidValue;
@@ -605,11 +652,12 @@ hipError_t launch_slice_fwd_bf(int spl, int nt, int variant, const SliceArgs& a,
 }
 
 hipError_t launch_pencil_bf(int spl, int nt, const PencilArgs& a, int max_blocks, int vps, int kpv,
-                            hipStream_t s) {
+                            hipStream_t s, const TaskTab& tt, int64_t items) {
   switch (nt) {
 #define C(n) \
   case n:    \
-    return spl == 2 ? pencil_nt<2, n>(a, max_blocks, vps, kpv, s) : pencil_nt<3, n>(a, max_blocks, vps, kpv, s);
+    return spl == 2 ? pencil_nt<2, n>(a, max_blocks, vps, kpv, s, tt, items) \
+                    : pencil_nt<3, n>(a, max_blocks, vps, kpv, s, tt, items);
     KX_NT_CASES(C)
 #undef C
     default: return hipErrorInvalidValue;
@@ -617,13 +665,13 @@ hipError_t launch_pencil_bf(int spl, int nt, const PencilArgs& a, int max_blocks
 }
 
 hipError_t launch_slice_inv_bf(int spl, int nt, int variant, const AccArgs& a, int64_t items,
-                               int max_blocks, int vps, int kpv, hipStream_t s) {
+                               int max_blocks, int vps, int kpv, hipStream_t s, const TaskTab& tt) {
   if (variant != SI_ACC12 && variant != SI_ST12) return hipErrorInvalidValue;
   switch (nt) {
 #define C(n)                                                                        \
   case n:                                                                           \
-    return spl == 2 ? inv_nt<2, n>(variant, a, items, max_blocks, vps, kpv, s)      \
-                    : inv_nt<3, n>(variant, a, items, max_blocks, vps, kpv, s);
+    return spl == 2 ? inv_nt<2, n>(variant, a, items, max_blocks, vps, kpv, s, tt)  \
+                    : inv_nt<3, n>(variant, a, items, max_blocks, vps, kpv, s, tt);
     KX_NT_CASES(C)
 #undef C
     default: return hipErrorInvalidValue;

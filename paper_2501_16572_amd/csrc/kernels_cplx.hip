@@ -156,9 +156,9 @@ __device__ __forceinline__ double cblock_sum(double v, double* red) {
 
 // Pass A: pair density (IN = 0) or load (IN = 1), V1^{*T} S, S V2^*.
 // a.V1, a.V2: (re, im) planes of V1, V2 (re plane at V, im plane at V + P*P).
-template <typename T, int NK, int IN>
+template <typename T, int NK, int IN, bool MT = false>
 __global__ void __launch_bounds__(CTiles<NK>::THREADS)
-k_slice_fwd_c(SliceArgs a) {
+k_slice_fwd_c(SliceArgs a0, TaskTab tt) {
   constexpr int NT = CTiles<NK>::NT, P = CTiles<NK>::P, LD = P + 1;
   constexpr int EPT = (16 * NK * NK + CTiles<NK>::THREADS - 1) / CTiles<NK>::THREADS;
   using M = Cm<T>;
@@ -166,15 +166,21 @@ k_slice_fwd_c(SliceArgs a) {
   __shared__ T Sr[P * LD], Si[P * LD];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
-  const T* V1 = (const T*)a.V1;
-  const T* V2 = (const T*)a.V2;
-  const int PP = a.P * a.P;
-  const int nk = (max(a.n1, a.n2) + 3) / 4;
   for (int i = tid; i < P * LD; i += nthr) Sr[i] = Si[i] = T(0);
   lds_barrier_c();
-  const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
-  const int64_t nitems = (int64_t)a.npairs * a.n3;
-  for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+  const int64_t total = MT ? tt.pre[tt.ntasks] : (int64_t)a0.npairs * a0.n3;
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    int64_t item = g;
+    SliceArgs a = a0;
+    if constexpr (MT) {
+      int t;
+      a = task_args<SliceArgs>(tt, g, item, t);
+    }
+    const T* V1 = (const T*)a.V1;
+    const T* V2 = (const T*)a.V2;
+    const int PP = a.P * a.P;
+    const int nk = (max(a.n1, a.n2) + 3) / 4;
+    const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
     const int p = (int)(item / a.n3), i3 = (int)(item - (int64_t)p * a.n3);
     const int64_t soff = (int64_t)i3 * a.n12;
     const C2<T>* pa;
@@ -222,9 +228,9 @@ k_slice_fwd_c(SliceArgs a) {
 
 // Pass B: Z = X V3^*, Z *= f, Y = Z V3^T on chunks of 64 pencils, in place.
 // a.V3 = planes of V3, a.V3T = planes of V3^T.
-template <typename T, int NK>
+template <typename T, int NK, bool MT = false>
 __global__ void __launch_bounds__(CTiles<NK>::THREADS)
-k_pencil_c(PencilArgs a) {
+k_pencil_c(PencilArgs a0, TaskTab tt) {
   constexpr int NT = CTiles<NK>::NT, P = CTiles<NK>::P;
   constexpr int QT = 4, Q = 64, LDQ = Q + 1;
   using M = Cm<T>;
@@ -232,16 +238,9 @@ k_pencil_c(PencilArgs a) {
   __shared__ T Sr[P * LDQ], Si[P * LDQ];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
-  const int chunk = blockIdx.x % a.nchunks;
-  const int pstep = gridDim.x / a.nchunks;
-  const int q0 = chunk * Q;
-  const int nk = (a.n3 + 3) / 4;
-  const int PP = a.P3 * a.P3;
-  const T* V3 = (const T*)a.V3;
-  const T* V3T = (const T*)a.V3T;
   for (int i = tid; i < P * LDQ; i += nthr) Sr[i] = Si[i] = T(0);
   double fr[QT][4];
-  {
+  auto load_f = [&](const PencilArgs& a, int q0) {
     const int c = 16 * w + lr;
 #pragma unroll
     for (int qt = 0; qt < QT; ++qt)
@@ -250,10 +249,13 @@ k_pencil_c(PencilArgs a) {
         const int q = q0 + 16 * qt + M::row(lg, r);
         fr[qt][r] = (q < a.n12 && c < a.n3) ? a.ftab[q + (int64_t)a.n12 * c] : 0.0;
       }
-  }
-  lds_barrier_c();
+  };
   constexpr int EPT = Q * P / CTiles<NK>::THREADS;
-  for (int p = blockIdx.x / a.nchunks; p < a.npairs; p += pstep) {
+  auto run = [&](const PencilArgs& a, int q0, int p) {
+    const int nk = (a.n3 + 3) / 4;
+    const int PP = a.P3 * a.P3;
+    const T* V3 = (const T*)a.V3;
+    const T* V3T = (const T*)a.V3T;
     C2<T>* base = (C2<T>*)a.T + (int64_t)p * a.ld;
     {
       C2<T> v[EPT];
@@ -309,15 +311,42 @@ k_pencil_c(PencilArgs a) {
         }
     }
     lds_barrier_c();
+  };
+  if constexpr (!MT) {
+    const int chunk = blockIdx.x % a0.nchunks;
+    const int pstep = gridDim.x / a0.nchunks;
+    const int q0 = chunk * Q;
+    load_f(a0, q0);
+    lds_barrier_c();
+    for (int p = blockIdx.x / a0.nchunks; p < a0.npairs; p += pstep) run(a0, q0, p);
+  } else {
+    // contiguous runs of (chunk, pair) items, the pair fastest (as the real kernel)
+    lds_barrier_c();
+    const int64_t total = tt.pre[tt.ntasks];
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * per, g1 = min(total, g0 + per);
+    int cur_t = -1, cur_c = -1;
+    for (int64_t g = g0; g < g1; ++g) {
+      int64_t item;
+      int t;
+      const PencilArgs a = task_args<PencilArgs>(tt, g, item, t);
+      const int chunk = (int)(item / a.npairs), p = (int)(item - (int64_t)chunk * a.npairs);
+      if (t != cur_t || chunk != cur_c) {
+        load_f(a, chunk * Q);
+        cur_t = t;
+        cur_c = chunk;
+      }
+      run(a, chunk * Q, p);
+    }
   }
 }
 
 // Pass C: V1 S (planes of V1^T in a.V1), S V2^T (planes of V2^T in a.V2);
 // ACC: vx_t -= sum_m occ[m] psi_m (.) phi_mt (complex, FP64) and the E_x
 // partial sum_r Re(conj(phi_t) dVx_t); else store.
-template <typename T, int NK, bool ACC>
+template <typename T, int NK, bool ACC, bool MT = false>
 __global__ void __launch_bounds__(CTiles<NK>::THREADS)
-k_slice_inv_c(AccArgs a) {
+k_slice_inv_c(AccArgs a0, TaskTab tt) {
   constexpr int NT = CTiles<NK>::NT, P = CTiles<NK>::P, LD = P + 1;
   constexpr int EPT = (16 * NK * NK + CTiles<NK>::THREADS - 1) / CTiles<NK>::THREADS;
   using M = Cm<T>;
@@ -326,16 +355,23 @@ k_slice_inv_c(AccArgs a) {
   __shared__ double red[16];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
-  const T* V1T = (const T*)a.V1;
-  const T* V2T = (const T*)a.V2;
-  const int PP = a.P * a.P;
-  const int nk = (max(a.n1, a.n2) + 3) / 4;
   for (int i = tid; i < P * LD; i += nthr) Sr[i] = Si[i] = T(0);
   lds_barrier_c();
-  const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
-  const int n_inner = ACC ? a.n_occ : 1;
-  const int64_t nitems = (int64_t)(ACC ? a.n_t : a.n_t * a.n_occ) * a.n3;
-  for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+  const int64_t total =
+      MT ? tt.pre[tt.ntasks] : (int64_t)(ACC ? a0.n_t : a0.n_t * a0.n_occ) * a0.n3;
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    int64_t item = g;
+    AccArgs a = a0;
+    if constexpr (MT) {
+      int t;
+      a = task_args<AccArgs>(tt, g, item, t);
+    }
+    const T* V1T = (const T*)a.V1;
+    const T* V2T = (const T*)a.V2;
+    const int PP = a.P * a.P;
+    const int nk = (max(a.n1, a.n2) + 3) / 4;
+    const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
+    const int n_inner = ACC ? a.n_occ : 1;
     const int u = (int)(item / a.n3), i3 = (int)(item - (int64_t)u * a.n3);
     const int64_t soff = (int64_t)i3 * a.n12;
     double wr[ACC ? NT : 1][4], wi[ACC ? NT : 1][4];
@@ -447,48 +483,57 @@ constexpr bool cslice_fits() {
 }
 
 template <typename T, int NK>
-hipError_t cfwd(int variant, const SliceArgs& a, int64_t items, int max_blocks, hipStream_t s) {
+hipError_t cfwd(int variant, const SliceArgs& a, int64_t items, int max_blocks, hipStream_t s,
+                const TaskTab& tt) {
   if constexpr (!cslice_fits<T, NK>()) {
     return hipErrorInvalidValue;
   } else {
     constexpr int TH = CTiles<NK>::THREADS;
-    void (*k)(SliceArgs) = variant == SF_PAIR12 ? k_slice_fwd_c<T, NK, 0> : k_slice_fwd_c<T, NK, 1>;
+    void (*k)(SliceArgs, TaskTab) = tt.ntasks ? k_slice_fwd_c<T, NK, 0, true>
+                                    : variant == SF_PAIR12 ? k_slice_fwd_c<T, NK, 0> : k_slice_fwd_c<T, NK, 1>;
     if (items <= 0) return hipSuccess;
     int64_t cap = (int64_t)c_resident(k, TH) * device_cu_count();
     if (max_blocks > 0) cap = std::min<int64_t>(cap, max_blocks);
-    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(1, std::min(items, cap))), dim3(TH), 0, s, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(1, std::min(items, cap))), dim3(TH), 0, s, a, tt);
     return hipGetLastError();
   }
 }
 
 template <typename T, int NK>
-hipError_t cpencil(const PencilArgs& a, int max_blocks, hipStream_t s) {
+hipError_t cpencil(const PencilArgs& a, int max_blocks, hipStream_t s, const TaskTab& tt, int64_t items) {
   if constexpr ((size_t)2 * CTiles<NK>::P * 65 * sizeof(T) + 256 > 160 * 1024) {
     return hipErrorInvalidValue;
   } else {
   constexpr int TH = CTiles<NK>::THREADS;
-  void (*k)(PencilArgs) = k_pencil_c<T, NK>;
-  if (a.npairs <= 0 || a.nchunks <= 0) return hipSuccess;
+  void (*k)(PencilArgs, TaskTab) = tt.ntasks ? k_pencil_c<T, NK, true> : k_pencil_c<T, NK>;
   int64_t cap = (int64_t)c_resident(k, TH) * device_cu_count();
   if (max_blocks > 0) cap = std::min<int64_t>(cap, max_blocks);
+  if (tt.ntasks) {
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(1, std::min(items, cap))), dim3(TH), 0, s, a, tt);
+    return hipGetLastError();
+  }
+  if (a.npairs <= 0 || a.nchunks <= 0) return hipSuccess;
   int64_t groups = std::max<int64_t>(1, cap / a.nchunks);
   groups = std::min<int64_t>(groups, a.npairs);
-  hipLaunchKernelGGL(k, dim3((unsigned)(groups * a.nchunks)), dim3(TH), 0, s, a);
+  hipLaunchKernelGGL(k, dim3((unsigned)(groups * a.nchunks)), dim3(TH), 0, s, a, tt);
   return hipGetLastError();
   }
 }
 
 template <typename T, int NK>
-hipError_t cinv(int variant, const AccArgs& a, int64_t items, int max_blocks, hipStream_t s) {
+hipError_t cinv(int variant, const AccArgs& a, int64_t items, int max_blocks, hipStream_t s,
+                const TaskTab& tt) {
   if constexpr (!cslice_fits<T, NK>()) {
     return hipErrorInvalidValue;
   } else {
     constexpr int TH = CTiles<NK>::THREADS;
-    void (*k)(AccArgs) = variant == SI_ACC12 ? k_slice_inv_c<T, NK, true> : k_slice_inv_c<T, NK, false>;
+    void (*k)(AccArgs, TaskTab) = tt.ntasks ? k_slice_inv_c<T, NK, true, true>
+                                  : variant == SI_ACC12 ? k_slice_inv_c<T, NK, true> : k_slice_inv_c<T, NK, false>;
     if (items <= 0) return hipSuccess;
     int64_t cap = (int64_t)c_resident(k, TH) * device_cu_count();
     if (max_blocks > 0) cap = std::min<int64_t>(cap, max_blocks);
-    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(1, std::min(items, cap))), dim3(TH), 0, s, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(1, std::min(items, cap))), dim3(TH), 0, s, a, tt);
     return hipGetLastError();
   }
 }
@@ -498,23 +543,24 @@ hipError_t cinv(int variant, const AccArgs& a, int64_t items, int max_blocks, hi
 }  // namespace
 
 hipError_t launch_slice_fwd_c(bool f64, int nk, int variant, const SliceArgs& a, int64_t items,
-                              int max_blocks, hipStream_t s) {
+                              int max_blocks, hipStream_t s, const TaskTab& tt) {
   if (variant != SF_PAIR12 && variant != SF_LOAD12) return hipErrorInvalidValue;
   switch (nk) {
 #define C(n) \
   case n:    \
-    return f64 ? cfwd<double, n>(variant, a, items, max_blocks, s) : cfwd<float, n>(variant, a, items, max_blocks, s);
+    return f64 ? cfwd<double, n>(variant, a, items, max_blocks, s, tt) : cfwd<float, n>(variant, a, items, max_blocks, s, tt);
     KX_CNK_CASES(C)
 #undef C
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks, hipStream_t s) {
+hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks, hipStream_t s,
+                           const TaskTab& tt, int64_t items) {
   switch (nk) {
 #define C(n) \
   case n:    \
-    return f64 ? cpencil<double, n>(a, max_blocks, s) : cpencil<float, n>(a, max_blocks, s);
+    return f64 ? cpencil<double, n>(a, max_blocks, s, tt, items) : cpencil<float, n>(a, max_blocks, s, tt, items);
     KX_CNK_CASES(C)
 #undef C
     default: return hipErrorInvalidValue;
@@ -522,12 +568,12 @@ hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks
 }
 
 hipError_t launch_slice_inv_c(bool f64, int nk, int variant, const AccArgs& a, int64_t items,
-                              int max_blocks, hipStream_t s) {
+                              int max_blocks, hipStream_t s, const TaskTab& tt) {
   if (variant != SI_ACC12 && variant != SI_ST12) return hipErrorInvalidValue;
   switch (nk) {
 #define C(n) \
   case n:    \
-    return f64 ? cinv<double, n>(variant, a, items, max_blocks, s) : cinv<float, n>(variant, a, items, max_blocks, s);
+    return f64 ? cinv<double, n>(variant, a, items, max_blocks, s, tt) : cinv<float, n>(variant, a, items, max_blocks, s, tt);
     KX_CNK_CASES(C)
 #undef C
     default: return hipErrorInvalidValue;

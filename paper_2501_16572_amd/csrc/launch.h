@@ -27,19 +27,23 @@ enum SliceInvVariant { SI_ACC12 = 0, SI_ST12, SI_ST2, SI_ST1 };
 
 // Each launcher picks a persistent grid of at most `max_blocks` blocks
 // (0 = as many as are co-resident on the device) for `items` work items and
-// returns the HIP status of the launch.
+// returns the HIP status of the launch.  With a task table (tt.ntasks > 0)
+// the launch runs every batch of the table, `a` is ignored, and `items` is
+// the table's total item count (for the pencil launchers: the sum over
+// entries of nchunks * npairs).
+constexpr TaskTab kNoTasks{nullptr, nullptr, 0};
 hipError_t launch_slice_fwd_f64(int nk, int variant, const SliceArgs& a, int64_t items,
-                                int max_blocks, hipStream_t s);
+                                int max_blocks, hipStream_t s, const TaskTab& tt = kNoTasks);
 hipError_t launch_pencil_f64(int nk, int variant, const PencilArgs& a, int max_blocks,
-                             hipStream_t s);
+                             hipStream_t s, const TaskTab& tt = kNoTasks, int64_t items = 0);
 hipError_t launch_slice_inv_f64(int nk, int variant, const AccArgs& a, int64_t items,
-                                int max_blocks, hipStream_t s);
+                                int max_blocks, hipStream_t s, const TaskTab& tt = kNoTasks);
 hipError_t launch_slice_fwd_f32(int nk, int variant, const SliceArgs& a, int64_t items,
-                                int max_blocks, hipStream_t s);
+                                int max_blocks, hipStream_t s, const TaskTab& tt = kNoTasks);
 hipError_t launch_pencil_f32(int nk, int variant, const PencilArgs& a, int max_blocks,
-                             hipStream_t s);
+                             hipStream_t s, const TaskTab& tt = kNoTasks, int64_t items = 0);
 hipError_t launch_slice_inv_f32(int nk, int variant, const AccArgs& a, int64_t items,
-                                int max_blocks, hipStream_t s);
+                                int max_blocks, hipStream_t s, const TaskTab& tt = kNoTasks);
 hipError_t launch_scale_f64(double* T, int64_t ld, int npairs, int64_t N, const double* ftab,
                             hipStream_t s);
 hipError_t launch_accumulate_f64(const AccArgs& a, int blocks_per_target, hipStream_t s);
@@ -50,11 +54,13 @@ hipError_t launch_ex_finalize(const double* partials, int n_t, int per_target,
 // per padded axis).  vps: element stride between the split parts of one
 // eigenvector operand; kpv: its K padding (32 * ceil(nt / 2)).
 hipError_t launch_slice_fwd_bf(int spl, int nt, int variant, const SliceArgs& a, int64_t items,
-                               int max_blocks, int vps, int kpv, hipStream_t s);
+                               int max_blocks, int vps, int kpv, hipStream_t s,
+                               const TaskTab& tt = kNoTasks);
 hipError_t launch_pencil_bf(int spl, int nt, const PencilArgs& a, int max_blocks, int vps, int kpv,
-                            hipStream_t s);
+                            hipStream_t s, const TaskTab& tt = kNoTasks, int64_t items = 0);
 hipError_t launch_slice_inv_bf(int spl, int nt, int variant, const AccArgs& a, int64_t items,
-                               int max_blocks, int vps, int kpv, hipStream_t s);
+                               int max_blocks, int vps, int kpv, hipStream_t s,
+                               const TaskTab& tt = kNoTasks);
 inline int bf_nt(int n) { return (n + 15) / 16; }
 inline int bf_kp(int nt) { return 32 * ((nt + 1) / 2); }
 inline int bf_lines(int nt) { return 16 * nt > bf_kp(nt) ? 16 * nt : bf_kp(nt); }
@@ -62,10 +68,11 @@ inline int bf_lines(int nt) { return 16 * nt > bf_kp(nt) ? 16 * nt : bf_kp(nt); 
 // Complex (Bloch) launchers: f64 selects complex128 data (else complex64).
 // V arguments point at (re, im) planes, each P x P.
 hipError_t launch_slice_fwd_c(bool f64, int nk, int variant, const SliceArgs& a, int64_t items,
-                              int max_blocks, hipStream_t s);
-hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks, hipStream_t s);
+                              int max_blocks, hipStream_t s, const TaskTab& tt = kNoTasks);
+hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks, hipStream_t s,
+                           const TaskTab& tt = kNoTasks, int64_t items = 0);
 hipError_t launch_slice_inv_c(bool f64, int nk, int variant, const AccArgs& a, int64_t items,
-                              int max_blocks, hipStream_t s);
+                              int max_blocks, hipStream_t s, const TaskTab& tt = kNoTasks);
 
 // Number of compute units of the current device (cached).
 int device_cu_count();

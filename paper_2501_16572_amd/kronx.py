@@ -33,7 +33,7 @@ FLAG_COMPLEX = 16
 EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_batched",
            "kx_plan_info", "kx_plan_tables", "kx_host_eig1d", "kx_host_fd_weights",
            "kx_last_error", "kx_trace_enable", "kx_trace_read", "kx_trace_name", "kx_autotune",
-           "kx_plan_tuning"]
+           "kx_plan_tuning", "kx_batched_schedule"]
 
 
 class KronxError(RuntimeError):
@@ -82,6 +82,7 @@ def load_library(path=None):
     lib.kx_trace_name.restype = ctypes.c_char_p
     lib.kx_autotune.argtypes = [vp, vp, i64, ci, vp, vp, i64, ci, vp]
     lib.kx_plan_tuning.argtypes = [vp, ip]
+    lib.kx_batched_schedule.argtypes = [ip]
     for name in EXPORTS:
         if name not in ("kx_last_error", "kx_trace_name"):
             getattr(lib, name).restype = ci
@@ -247,6 +248,14 @@ def exx_apply_batched(tasks, stream=None):
                        t["phi"].shape[0], pv, ldv, ex.data_ptr() if ex is not None else None,
                        gphi.data_ptr() if gphi is not None else None)
     _check(load_library().exx_apply_batched(arr, len(tasks), _stream(stream)), "exx_apply_batched")
+
+
+def kx_batched_schedule():
+    """Shape of the last captured exx_apply_batched schedule:
+    (rounds, batches, launches of the three passes, most batches in one launch)."""
+    out = (ctypes.c_int * 4)()
+    _check(load_library().kx_batched_schedule(out), "kx_batched_schedule")
+    return tuple(out)
 
 
 TRACE_KINDS = 23

@@ -1,0 +1,194 @@
+"""Batched exchange (exx_apply_batched) with grouped persistent launches.
+
+Batches of several tasks whose plans share a kernel instantiation run as one
+launch over a task table.  Each item of such a launch does the arithmetic of
+the single-batch kernel in the same order, so the batched results are compared
+with per-task exx_apply calls (FP64 to 1e-14 relative, FP32 / split-BF16 to
+1e-6 of the FP64 scale), and the k-point set against the FP64 oracle
+(1e-12 / 1e-6).  The schedule shape (rounds, launches, widest launch) is
+checked through kx_batched_schedule so that grouping is known to happen.
+"""
+
+import numpy as np
+import pytest
+
+from oracle.exx import vx_apply_kpoints
+from oracle.kron import KronSolver
+from paper_2501_16572_amd.workloads import fermi_occupations, random_orbitals
+
+from gpu_util import rel_fro, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BCP = ("periodic",) * 3
+
+
+@pytest.fixture(scope="module")
+def kx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_16572_amd import kronx
+    kronx.load_library()
+    return kronx
+
+
+def _eager(kx, task):
+    vx = torch.zeros_like(task["vx"])
+    ex = torch.zeros(1, dtype=torch.float64, device="cuda")
+    kx.exx_apply(task["plan"], task["psi"], task["occ"], task["phi"], vx, ex=ex, gphi=task["gphi"])
+    return vx, ex
+
+
+def _rel(a, b):
+    return float((a - b).norm() / max(float(b.norm()), 1e-300))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_kpoint_set_one_launch_per_round(kx, prec):
+    # 2 k-points x 2 q-points on one grid: four complex plans (one per k - q).
+    # Tasks of one k write the same Vx, so the schedule has two rounds, each
+    # running two batches per pass in a single launch.
+    n, h = (16, 18, 14), (0.35, 0.35, 0.35)
+    say("batched k-points", prec)
+    L = [n[d] * h[d] for d in range(3)]
+    kpts = [(2 * np.pi / L[0] * 0.25, 2 * np.pi / L[1] * 0.25, 0.0),
+            (-2 * np.pi / L[0] * 0.25, 2 * np.pi / L[1] * 0.25, 0.0)]
+    wk = [0.5, 0.5]
+    psi = [random_orbitals(n, h, 5, seed=80 + i, kpt=k, decay=2.0) for i, k in enumerate(kpts)]
+    g = [np.array([1.0, 1.0, 0.7, 0.0, 0.0])] * 2
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec == "fp32":
+        psi = [p.astype(np.complex64).astype(np.complex128) for p in psi]
+    plans = []
+    try:
+        dev_psi = [to_dev(p, ct) for p in psi]
+        vx = [torch.zeros((5, psi[0].shape[1]), dtype=torch.complex128, device="cuda") for _ in range(2)]
+        ex = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2)]
+        tasks = []
+        for ik in range(2):
+            gphi = to_dev(g[ik] * wk[ik], torch.float64)
+            for iq in range(2):
+                kq = tuple(kpts[ik][d] - kpts[iq][d] for d in range(3))
+                plan = kx.kron_setup(n, h, BCP, 12, 0.0, kq=kq, prec=prec, complex=True)
+                plans.append(plan)
+                occ = to_dev(wk[iq] * g[iq][:3], torch.float64)
+                tasks.append(dict(plan=plan, psi=dev_psi[iq][:3], occ=occ, phi=dev_psi[ik], vx=vx[ik],
+                                  ex=ex[ik], gphi=gphi))
+        results = []
+        for rep in range(2):
+            for ik in range(2):
+                vx[ik].zero_()
+                ex[ik].zero_()
+            kx.exx_apply_batched(tasks)
+            torch.cuda.synchronize()
+            results.append(([to_host(v) for v in vx], [float(to_host(e)[0]) for e in ex]))
+        rounds, batches, launches, widest = kx.kx_batched_schedule()
+        assert (rounds, batches, launches, widest) == (2, 4, 6, 2), (rounds, batches, launches, widest)
+    finally:
+        for p in plans:
+            p.destroy()
+    # replays are bitwise identical
+    for ik in range(2):
+        assert np.array_equal(results[0][0][ik], results[1][0][ik])
+        assert results[0][1][ik] == results[1][1][ik]
+
+    def solver_for(ik, iq):
+        kq = tuple(kpts[ik][d] - kpts[iq][d] for d in range(3))
+        return KronSolver(n, h, BCP, 12, 0.0, kq)
+
+    W = vx_apply_kpoints(psi, g, wk, solver_for)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    out, exv = results[0]
+    for ik in range(2):
+        assert rel_fro(out[ik], W[ik]) < tol, ik
+        Eref = wk[ik] * float(np.sum(g[ik] * np.real(np.sum(np.conj(psi[ik]) * W[ik], axis=1)))) * np.prod(h)
+        assert abs(exv[ik] - Eref) < 10 * tol * abs(Eref), (exv[ik], Eref)
+
+
+# uneven Gamma systems: (grid, h, omega, bands, occupied, seed); the first two
+# share the x1/x2 and x3 tile counts, the last two share the x1/x2 one
+SYSTEMS = [((24, 24, 24), 0.3, 0.0, 6, 4, 91), ((22, 20, 24), 0.3, 0.106, 5, 4, 92),
+           ((40, 36, 44), 0.28, 0.106, 4, 3, 93), ((36, 40, 30), 0.3, 0.0, 4, 3, 94)]
+
+
+def _gamma_tasks(kx, prec, systems):
+    dt = {"fp64": torch.float64}.get(prec, torch.float32)
+    plans, tasks = [], []
+    for n, h, omega, nb, no, seed in systems:
+        psi = random_orbitals(n, (h,) * 3, nb, seed=seed)
+        g = fermi_occupations(nb, no, 0.01, seed=seed)
+        plan = kx.kron_setup(n, (h,) * 3, BCP, 12, omega, prec=prec)
+        plans.append(plan)
+        psid = to_dev(psi, dt)
+        tasks.append(dict(plan=plan, psi=psid[:no], occ=to_dev(g[:no], torch.float64), phi=psid,
+                          vx=torch.zeros(psid.shape, dtype=torch.float64, device="cuda"),
+                          ex=torch.zeros(1, dtype=torch.float64, device="cuda"),
+                          gphi=to_dev(g, torch.float64)))
+    return plans, tasks
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
+def test_uneven_systems_ragged_batches(kx, prec, monkeypatch):
+    # a small workspace cuts every task into several batches of uneven size,
+    # so rounds hold batches of different systems and ragged last batches
+    say("batched uneven systems", prec)
+    monkeypatch.setenv("KX_WORKSPACE_MB", "1")
+    plans, tasks = _gamma_tasks(kx, prec, SYSTEMS)
+    try:
+        ref = [_eager(kx, t) for t in tasks]
+        for rep in range(2):
+            for t in tasks:
+                t["vx"].zero_()
+                t["ex"].zero_()
+            kx.exx_apply_batched(tasks)
+            torch.cuda.synchronize()
+            tol = 1e-14 if prec == "fp64" else 1e-6
+            for i, (t, (vx_e, ex_e)) in enumerate(zip(tasks, ref)):
+                assert _rel(t["vx"], vx_e) < tol, (rep, i, _rel(t["vx"], vx_e))
+                assert abs(float(t["ex"][0] - ex_e[0])) <= tol * abs(float(ex_e[0])), (rep, i)
+        rounds, batches, launches, widest = kx.kx_batched_schedule()
+        assert batches > len(SYSTEMS) and rounds >= 2
+        assert widest >= 2 and launches < 3 * batches, (rounds, batches, launches, widest)
+    finally:
+        for p in plans:
+            p.destroy()
+
+
+def test_shared_plan_and_oracle(kx, monkeypatch):
+    # one plan used by two tasks (its bands split in two) next to a second
+    # system: the two halves never share a round (one workspace), and the
+    # result matches the FP64 oracle
+    say("batched shared plan")
+    monkeypatch.setenv("KX_WORKSPACE_MB", "2")
+    n, h, omega, nb, no, seed = (24, 24, 24), 0.3, 0.106, 6, 4, 95
+    psi = random_orbitals(n, (h,) * 3, nb, seed=seed)
+    g = fermi_occupations(nb, no, 0.01, seed=seed)
+    plans, tasks2 = _gamma_tasks(kx, "fp64", [SYSTEMS[1]])
+    plan = kx.kron_setup(n, (h,) * 3, BCP, 12, omega, prec="fp64")
+    plans.append(plan)
+    try:
+        psid = to_dev(psi, torch.float64)
+        occ = to_dev(g[:no], torch.float64)
+        vx = torch.zeros_like(psid)
+        ex = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gphi = to_dev(g, torch.float64)
+        tasks = [dict(plan=plan, psi=psid[:no], occ=occ, phi=psid[:3], vx=vx[:3], ex=ex, gphi=gphi[:3]),
+                 tasks2[0],
+                 dict(plan=plan, psi=psid[:no], occ=occ, phi=psid[3:], vx=vx[3:], ex=ex, gphi=gphi[3:])]
+        kx.exx_apply_batched(tasks)
+        torch.cuda.synchronize()
+        rounds, batches, launches, widest = kx.kx_batched_schedule()
+        assert rounds >= 2 and widest >= 2, (rounds, batches, launches, widest)
+        S = KronSolver(n, (h,) * 3, BCP, 12, omega)
+        from oracle.exx import exchange_energy, vx_apply
+        W = vx_apply(psi[:no], g[:no], psi, S)
+        assert rel_fro(to_host(vx), W) < 1e-12
+        E = exchange_energy(psi, g, W, S.dV)
+        assert abs(float(to_host(ex)[0]) - E) < 1e-12 * abs(E)
+        vx_e, ex_e = _eager(kx, tasks2[0])
+        assert _rel(tasks2[0]["vx"], vx_e) < 1e-14
+    finally:
+        for p in plans:
+            p.destroy()
