@@ -115,6 +115,69 @@ CONFIGS = {
 }
 
 
+# Several plans in one batched call: a 2x2x1 Monkhorst-Pack k-point set on an
+# 80^3 grid (Coulomb kernel; Bloch phase k - q, four distinct operators up to
+# reciprocal lattice vectors) and six Gamma-point systems of uneven sizes
+# (erfc kernel).  h = 0.25 bohr; 3/4 of the bands occupied.
+BATCH5 = dict(
+    kind="batched", prec="fp32",
+    kgrid=dict(n=(80, 80, 80), h=(0.25, 0.25, 0.25), bc=("periodic",) * 3, order=12, omega=0.0,
+               n_b=160, n_occ=120, kT=0.01, seed=50, mp=(2, 2, 1)),
+    systems=[((48, 48, 48), 64, 48), ((56, 56, 56), 96, 72), ((64, 64, 64), 128, 96),
+             ((64, 64, 96), 128, 96), ((72, 72, 72), 160, 120), ((90, 90, 90), 192, 144)],
+    h=0.25, omega=OMEGA_HSE, order=12, kT=0.01, seed=51)
+CONFIGS["batch5"] = BATCH5
+
+
+def monkhorst_pack(n, h, mp):
+    """k-points (2 pi / L_d) * ((2 i - m_d + 1) / (2 m_d)) of an m1 x m2 x m3
+    Monkhorst-Pack set (no shift beyond the standard one) and equal weights."""
+    L = [n[d] * h[d] for d in range(3)]
+    axes = [[2.0 * np.pi / L[d] * (2 * i - mp[d] + 1) / (2.0 * mp[d]) for i in range(mp[d])]
+            for d in range(3)]
+    ks = [(a, b, c) for c in axes[2] for b in axes[1] for a in axes[0]]
+    return ks, [1.0 / len(ks)] * len(ks)
+
+
+def bloch_class(kq, n, h):
+    """Representative of the Bloch vector k - q modulo reciprocal lattice
+    vectors (2 pi / L_d): the FD operator depends on it only through the
+    boundary phase exp(i kappa_d L_d)."""
+    out = []
+    for d in range(3):
+        G = 2.0 * np.pi / (n[d] * h[d])
+        r = float(np.mod(kq[d], G))
+        if abs(r - G) < 1e-12 * G or abs(r) < 1e-12 * G:
+            r = 0.0
+        out.append(r)
+    return tuple(out)
+
+
+def make_batch_inputs(cfg):
+    """Inputs of the batched workload.
+
+    Returns (kpart, systems): kpart = dict(kpts, wk, psi (list of (n_b, N)
+    complex128), g (list of (n_b,))); systems = list of dicts with n, h, psi
+    (n_b, N) float64, g (n_b,) and n_occ.
+    """
+    kg = cfg["kgrid"]
+    ks, wk = monkhorst_pack(kg["n"], kg["h"], kg["mp"])
+    rng = np.random.default_rng(kg["seed"])
+    psi_k, g_k = [], []
+    for k in ks:
+        psi_k.append(random_orbitals(kg["n"], kg["h"], kg["n_b"], seed=None, rng=rng, kpt=k))
+        g_k.append(fermi_occupations(kg["n_b"], kg["n_occ"], kg["kT"], seed=None, rng=rng))
+    kpart = dict(kpts=ks, wk=wk, psi=psi_k, g=g_k, n_occ=kg["n_occ"])
+    systems = []
+    for i, (n, nb, no) in enumerate(cfg["systems"]):
+        rng = np.random.default_rng(cfg["seed"] + i)
+        h = (cfg["h"],) * 3
+        psi = random_orbitals(n, h, nb, seed=None, rng=rng)
+        g = fermi_occupations(nb, no, cfg["kT"], seed=None, rng=rng)
+        systems.append(dict(n=n, h=h, psi=psi, g=g, n_occ=no))
+    return kpart, systems
+
+
 def make_inputs(cfg, n_b=None, dtype=np.float64):
     """Orbitals (n_b, N) and occupations (n_b,) for a Gamma-point workload.
 
