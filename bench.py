@@ -17,6 +17,7 @@ and the oracle timed on the host on a bounded sample.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +29,35 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "bf16x6": 2500.0 / 6}
 METRIC = "Poisson solves/s + MFMA TFLOP/s in exx_apply, mixed vs FP64, at stated err"
+
+
+def kernel_sources_sha256():
+    """Hash of the library's device and host sources: measured counters are
+    valid only for the code they were taken on."""
+    d = os.path.join(ROOT, "paper_2501_16572_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".inc", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, form, kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none for this kernel or the
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    e = rec.get("kernels", {}).get(f"{form}/{kernel}")
+    return None if e is None else e.get("hbm_bytes_per_launch")
 
 
 def log(*a):
@@ -308,7 +338,9 @@ def main():
         ms_tot, launches = kern[dom]
         achieved = flops[dom] / (ms_tot / 1e3) / 1e12
         roof = dict(bound="mfma", kernel=dom, achieved=achieved, peak=PEAK_TFLOPS[prec],
-                    unit="TFLOP/s", frac=achieved / PEAK_TFLOPS[prec], traffic=None,
+                    unit="TFLOP/s", frac=achieved / PEAK_TFLOPS[prec],
+                    traffic=measured_traffic(args.workload, f"{prec}:{path}", dom),
+                    traffic_unit="HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     avg_launch_ms=ms_tot / launches, launches=launches)
 
     # accuracy of the headline result on sampled bands against the oracle

@@ -229,26 +229,27 @@ const char* kx_trace_name(int kind);
 
 /* kx_autotune -- choose the launch configuration of the three fused passes
  * for this plan and workload (the batch Kronecker solve's analogue of the
- * batch size n_c, Sec. II.B): for each candidate (occupancy variant x
- * resident blocks per CU) it runs passes A, B, C on the first batch that
- * exx_apply would make of the given data (as many target columns as the
- * workspace holds), times every pass with HIP events, and keeps the fastest
- * candidate per pass in the plan (later exx_apply calls on any stream use
- * it).  Arguments as exx_apply; nothing the caller owns is written (a private
- * Vx buffer of one batch receives the results).  Synchronous; costs about
- * twenty batches of device time once per key.
- * If the environment variable KX_TUNE_CACHE names a file, choices are read
- * from and appended to it (one line per key: arch, grid, precision, complex
- * flag, n_occ), and a cached key skips the timing.  The occupancy variant
- * exists for real FP64/FP32 plans; complex and split-BF16 plans tune the
- * resident blocks per CU only. */
+ * batch size n_c, Sec. II.B): for each candidate (variant bits x resident
+ * blocks per CU, see kx_plan_tuning) it runs passes A, B, C on the first
+ * batch that exx_apply would make of the given data (as many target columns
+ * as the workspace holds), times every pass with HIP events, and keeps the
+ * fastest candidate per pass in the plan (later exx_apply calls on any
+ * stream use it).  Arguments as exx_apply; nothing the caller owns is written
+ * (a private Vx buffer of one batch receives the results).  Synchronous;
+ * costs two batches of device time per candidate (20 candidates for real
+ * FP64/FP32 plans, 5 for complex and split-BF16 plans, which tune the
+ * resident blocks per CU only), once per key.  If the environment variable
+ * KX_TUNE_CACHE names a file, choices are read from and appended to it (one
+ * line per key: arch, grid, precision, complex flag, n_occ), and a cached key
+ * skips the timing. */
 kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, const double* d_occ,
                       const void* d_phi, int64_t ld_phi, int n_b, void* stream);
 
 /* kx_plan_tuning -- the plan's current launch configuration per fused pass:
- * out[2*i] = occupancy variant (0/1), out[2*i+1] = resident blocks per CU
- * (0 = as many as fit), for passes i = A, B, C; out[6] = 1 if it came from
- * kx_autotune (timed or cached). */
+ * out[2*i] = variant bits (bit 0: alternative occupancy target; bit 1, passes
+ * A and C: mode-2 product computed transposed, x1 along the MFMA columns),
+ * out[2*i+1] = resident blocks per CU (0 = as many as fit), for passes
+ * i = A, B, C; out[6] = 1 if it came from kx_autotune (timed or cached). */
 kx_status kx_plan_tuning(kx_plan p, int out[7]);
 
 /* kx_last_error -- text for this thread's last non-OK status ("" if none).

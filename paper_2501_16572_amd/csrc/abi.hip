@@ -282,9 +282,16 @@ int bf_spl(const kx_plan p) { return p->prec == KX_PREC_BF16X3 ? 2 : 3; }
 int tuned_blocks(const kx_plan p, int pass) {
   return p->tune_bpc[pass] > 0 ? p->tune_bpc[pass] * kx::device_cu_count() : p->max_blocks;
 }
+// Launch variant bits of pass `pass` (bit 0: alternative occupancy target;
+// bit 1: transposed mode-2 product, passes A and C only) for the FP64/FP32
+// real kernels; the other kernel families have one variant.
 int tuned_variant(const kx_plan p, int pass, int variant) {
   const bool real_mfma = !p->cplx && (p->prec == KX_PREC_FP64 || p->prec == KX_PREC_FP32);
-  return (real_mfma && p->tune_tv[pass]) ? (variant | kx::TUNE_ALT) : variant;
+  if (!real_mfma) return variant;
+  const int bits = p->tune_tv[pass];
+  if (bits & 1) variant |= kx::TUNE_ALT;
+  if ((bits & 2) && pass != 1) variant |= kx::TUNE_TR;
+  return variant;
 }
 
 // The argument structs as the kernels of plan p read them: split-BF16 plans
@@ -399,20 +406,29 @@ BatchArgs batch_args(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, cons
   return b;
 }
 
-// Targets per batch that the plan's buffers hold (prepare_exx sized them).
+// n_b targets in batches of at most `cap`: as few batches as that allows, of
+// equal size up to one target (a small ragged last batch would leave most of
+// the device idle in its launches).
+int balanced_batch(int n_b, size_t cap) {
+  cap = std::max<size_t>(1, std::min<size_t>(cap, (size_t)n_b));
+  const size_t nbatch = ((size_t)n_b + cap - 1) / cap;
+  return (int)(((size_t)n_b + nbatch - 1) / nbatch);
+}
+
+// Targets per batch within what the plan's buffers hold (prepare_exx sized
+// them), balanced over the batches; 0 if the buffers hold no target.
 int held_batch(const kx_plan p, int n_occ, int n_b) {
   const size_t per_t_ws = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
   const size_t per_t_part = std::max<size_t>(64, (size_t)p->n[2]) * sizeof(double);
   const size_t cap = std::min(p->ws_bytes / per_t_ws, p->part_bytes / per_t_part);
-  return (int)std::min<size_t>(cap, (size_t)n_b);
+  return cap == 0 ? 0 : balanced_batch(n_b, cap);
 }
 
 // Enqueue one exx_apply.  Arguments already validated; buffers allocated for
 // the batch size returned by batch_targets().
 int batch_targets(kx_plan p, int n_occ, int n_b) {
   const size_t per_t = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
-  size_t nt = std::max<size_t>(1, workspace_limit() / std::max<size_t>(per_t, 1));
-  return (int)std::min<size_t>(nt, (size_t)n_b);
+  return balanced_batch(n_b, workspace_limit() / std::max<size_t>(per_t, 1));
 }
 
 kx_status prepare_exx(kx_plan p, int n_occ, int n_b, int path) {
@@ -944,17 +960,20 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
   const int ns = n_b;
   st = prepare_exx(p, n_occ, ns, KX_PATH_FUSED);
   if (st != KX_OK) return st;
-  const size_t per_t = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
-  const int cur = (int)std::min<size_t>((size_t)ns, p->ws_bytes / per_t);
+  const int cur = held_batch(p, n_occ, ns);
+  if (cur < 1) return fail(KX_ESTATE, "kx_autotune: workspace not prepared");
   double* vx = nullptr;
   if (hipMalloc((void**)&vx, (size_t)cur * p->N * sizeof(double) * (p->cplx ? 2 : 1)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(KX_ENOMEM, "kx_autotune: sample Vx buffer");
   }
   // candidates: (occupancy variant, resident blocks per CU; 0 = all that fit)
-  static const int cand[][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {0, 4},
-                                {1, 0}, {1, 1}, {1, 2}, {1, 3}, {1, 4}};
-  const int ncand = real_mfma ? 10 : 5;  // the occupancy variant exists for FP64/FP32 real kernels
+  // (variant bits, resident blocks per CU); the variant bits exist for the
+  // FP64/FP32 real kernels only
+  static const int cand[][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {0, 4}, {1, 0}, {1, 1},
+                                {1, 2}, {1, 3}, {1, 4}, {2, 0}, {2, 1}, {2, 2}, {2, 3},
+                                {2, 4}, {3, 0}, {3, 1}, {3, 2}, {3, 3}, {3, 4}};
+  const int ncand = real_mfma ? 20 : 5;
   hipEvent_t ev[4];
   for (int i = 0; i < 4; ++i) hipEventCreate(&ev[i]);
   float best[3] = {1e30f, 1e30f, 1e30f};
