@@ -177,6 +177,16 @@ typedef struct {
  * precision.  Results are bitwise reproducible across replays. */
 kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream);
 
+/* kx_workspace_bytes -- device bytes that exx_apply (or a batched task) on
+ * plan p with n_b targets and n_occ occupied orbitals holds: one batch of
+ * pair intermediates (targets per batch x n_occ x N elements of the plan's
+ * type, batches balanced within the workspace limit: min(32 GiB, 40 % of
+ * free device memory) or KX_WORKSPACE_MB) plus the E_x partials.  The plan
+ * allocates them at its first such call, grows them when a later call needs
+ * more, and frees them in kron_destroy.  Host only, no allocation.
+ * *bytes = 0 when n_b or n_occ is 0. */
+kx_status kx_workspace_bytes(kx_plan p, int n_b, int n_occ, int64_t* bytes);
+
 /* kx_batched_schedule -- shape of the schedule that the last capture of
  * exx_apply_batched in this process built: out[0] = rounds, out[1] = batches
  * (one task contributes ceil(n_b / targets per batch)), out[2] = launches of

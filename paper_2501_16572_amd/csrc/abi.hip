@@ -1285,6 +1285,20 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
   return KX_OK;
 }
 
+kx_status kx_workspace_bytes(kx_plan p, int n_b, int n_occ, int64_t* bytes) {
+  if (!p || !bytes) return fail(KX_EINVAL, "kx_workspace_bytes: NULL argument");
+  if (n_b < 0 || n_occ < 0) return fail(KX_EINVAL, "kx_workspace_bytes: negative size");
+  if (n_b == 0 || n_occ == 0) {
+    *bytes = 0;
+    return KX_OK;
+  }
+  const int nt = batch_targets(p, n_occ, n_b);
+  const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+  const size_t part = (size_t)nt * std::max<size_t>(64, (size_t)p->n[2]) * sizeof(double);
+  *bytes = (int64_t)((size_t)nt * n_occ * p->N * eb + part);
+  return KX_OK;
+}
+
 kx_status kx_batched_schedule(int out[4]) {
   if (!out) return fail(KX_EINVAL, "kx_batched_schedule: NULL argument");
   std::lock_guard<std::mutex> lock(g_graph_mu);

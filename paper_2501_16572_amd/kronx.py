@@ -33,7 +33,7 @@ FLAG_COMPLEX = 16
 EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_batched",
            "kx_plan_info", "kx_plan_tables", "kx_host_eig1d", "kx_host_fd_weights",
            "kx_last_error", "kx_trace_enable", "kx_trace_read", "kx_trace_name", "kx_autotune",
-           "kx_plan_tuning", "kx_batched_schedule"]
+           "kx_plan_tuning", "kx_batched_schedule", "kx_workspace_bytes"]
 
 
 class KronxError(RuntimeError):
@@ -83,6 +83,7 @@ def load_library(path=None):
     lib.kx_autotune.argtypes = [vp, vp, i64, ci, vp, vp, i64, ci, vp]
     lib.kx_plan_tuning.argtypes = [vp, ip]
     lib.kx_batched_schedule.argtypes = [ip]
+    lib.kx_workspace_bytes.argtypes = [vp, ci, ci, ctypes.POINTER(i64)]
     for name in EXPORTS:
         if name not in ("kx_last_error", "kx_trace_name"):
             getattr(lib, name).restype = ci
@@ -251,6 +252,14 @@ def exx_apply_batched(tasks, stream=None):
                        t["phi"].shape[0], pv, ldv, ex.data_ptr() if ex is not None else None,
                        gphi.data_ptr() if gphi is not None else None)
     _check(load_library().exx_apply_batched(arr, len(tasks), _stream(stream)), "exx_apply_batched")
+
+
+def kx_workspace_bytes(plan, n_b, n_occ):
+    """Device bytes exx_apply on `plan` holds for n_b targets x n_occ occupied."""
+    out = ctypes.c_int64(0)
+    _check(load_library().kx_workspace_bytes(plan.handle, n_b, n_occ, ctypes.byref(out)),
+           "kx_workspace_bytes")
+    return out.value
 
 
 def kx_batched_schedule():

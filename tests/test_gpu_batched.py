@@ -192,3 +192,30 @@ def test_shared_plan_and_oracle(kx, monkeypatch):
     finally:
         for p in plans:
             p.destroy()
+
+
+def test_workspace_bytes_and_balanced_batches(kx, monkeypatch):
+    # 1 MiB of workspace holds 2 targets x 4 occupied of a 24^3 FP64 grid:
+    # 5 targets run as 3 balanced batches of 2, and kx_workspace_bytes states
+    # the buffers exx_apply then holds
+    say("workspace bytes")
+    monkeypatch.setenv("KX_WORKSPACE_MB", "1")
+    n, h, nb, no = (24, 24, 24), (0.3,) * 3, 5, 4
+    N = n[0] * n[1] * n[2]
+    psi = random_orbitals(n, h, nb, seed=96)
+    g = fermi_occupations(nb, no, 0.01, seed=96)
+    plan = kx.kron_setup(n, h, BCP, 12, 0.106, prec="fp64")
+    try:
+        assert kx.kx_workspace_bytes(plan, 0, no) == 0
+        wb = kx.kx_workspace_bytes(plan, nb, no)
+        assert wb == 2 * no * N * 8 + 2 * 64 * 8, wb
+        psid = to_dev(psi, torch.float64)
+        vx = torch.zeros_like(psid)
+        kx.exx_apply(plan, psid[:no], to_dev(g[:no], torch.float64), psid, vx)
+        torch.cuda.synchronize()
+        assert plan.info()[7] == 2
+        S = KronSolver(n, h, BCP, 12, 0.106)
+        from oracle.exx import vx_apply
+        assert rel_fro(to_host(vx), vx_apply(psi[:no], g[:no], psi, S)) < 1e-12
+    finally:
+        plan.destroy()
