@@ -246,7 +246,7 @@ const char* kx_trace_name(int kind);
  * fastest candidate per pass in the plan (later exx_apply calls on any
  * stream use it).  Arguments as exx_apply; nothing the caller owns is written
  * (a private Vx buffer of one batch receives the results).  Synchronous;
- * costs two batches of device time per candidate (20 candidates for real
+ * costs two batches of device time per candidate (23 candidates for real
  * FP64/FP32 plans, 5 for complex and split-BF16 plans, which tune the
  * resident blocks per CU only), once per key.  If the environment variable
  * KX_TUNE_CACHE names a file, choices are read from and appended to it (one
@@ -257,7 +257,9 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
 
 /* kx_plan_tuning -- the plan's current launch configuration per fused pass:
  * out[2*i] = variant bits (bit 0: alternative occupancy target; bit 1, passes
- * A and C: mode-2 product computed transposed, x1 along the MFMA columns),
+ * A and C: mode-2 product computed transposed, x1 along the MFMA columns;
+ * bit 2, passes B and C: eigenvector matrices resident in LDS, the next work
+ * item's data prefetched into registers; it overrides bits 0 and 1),
  * out[2*i+1] = resident blocks per CU (0 = as many as fit), for passes
  * i = A, B, C; out[6] = 1 if it came from kx_autotune (timed or cached). */
 kx_status kx_plan_tuning(kx_plan p, int out[7]);

@@ -22,7 +22,9 @@ enum SliceFwdVariant { SF_PAIR12 = 0, SF_LOAD12, SF_PAIR, SF_LOAD1, SF_LOAD2 };
 // OR-ed into a fused variant by the autotuner: TUNE_ALT selects the
 // alternative occupancy target of the same kernel, TUNE_TR the transposed
 // mode-2 product of the slice passes (x1 along the MFMA columns).
-enum { TUNE_ALT = 64, TUNE_TR = 128 };
+// TUNE_VL selects the pass-B / pass-C kernels with the eigenvector matrices
+// resident in LDS (where they fit; elsewhere the streamed kernel runs).
+enum { TUNE_ALT = 64, TUNE_TR = 128, TUNE_VL = 256 };
 enum PencilVariant { PC_FSI = 0, PC_F, PC_I };
 enum SliceInvVariant { SI_ACC12 = 0, SI_ST12, SI_ST2, SI_ST1 };
 

@@ -158,7 +158,8 @@ class Plan:
         """{pass: (variant bits, blocks per CU)} and whether it was autotuned.
 
         Variant bits: 1 = alternative occupancy target, 2 = transposed mode-2
-        product (passes A and C)."""
+        product (passes A and C), 4 = eigenvector matrices resident in LDS
+        (passes B and C)."""
         out = (ctypes.c_int * 7)()
         _check(load_library().kx_plan_tuning(self.handle, out), "kx_plan_tuning")
         return {"A": (out[0], out[1]), "B": (out[2], out[3]), "C": (out[4], out[5]),

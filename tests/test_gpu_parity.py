@@ -447,3 +447,67 @@ def test_autotune_choice_keeps_parity(kx, prec, tmp_path):
     S = KronSolver(n, h, BCP, 12, 0.106)
     Wref = vx_apply(psi_in[:5], g[:5], psi_in, S)
     assert rel_fro(W, Wref) < (1e-12 if prec == "fp64" else 1e-6)
+
+
+def _forced_plan(kx, n, h, omega, prec, bits, bpc, psi_d, occ_d, cache):
+    """A plan whose three passes run launch variant `bits` with `bpc` blocks
+    per CU, set through the tuning cache (the key is taken from a first
+    tuning run on the same shape)."""
+    import os
+    os.environ["KX_TUNE_CACHE"] = str(cache)
+    if not cache.exists():
+        p0 = kx.kron_setup(n, h, BCP, 12, omega, prec=prec)
+        kx.kx_autotune(p0, psi_d[:occ_d.shape[0]], occ_d, psi_d)
+        p0.destroy()
+    key = cache.read_text().split()[0]
+    with open(cache, "a") as f:
+        f.write(f"{key} {bits} {bpc} {bits} {bpc} {bits} {bpc}\n")
+    plan = kx.kron_setup(n, h, BCP, 12, omega, prec=prec)
+    kx.kx_autotune(plan, psi_d[:occ_d.shape[0]], occ_d, psi_d)
+    assert plan.tuning()["A"] == (bits, bpc)
+    return plan
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [(40, 36, 44), (72, 68, 70)])
+def test_every_launch_variant_keeps_parity(kx, prec, n, tmp_path, monkeypatch):
+    # variant bits: 1 occupancy target, 2 transposed mode-2 product (A, C),
+    # 4 eigenvector matrices in LDS (B, C); each against the oracle, and the
+    # LDS form also in a grouped (task-table) batched launch of two plans
+    h, omega = (0.3, 0.3, 0.3), 0.106
+    say("variants", prec, n)
+    monkeypatch.setenv("KX_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    nb, no = 3, 2
+    psi = random_orbitals(n, h, nb, seed=97)
+    g = fermi_occupations(nb, no, 0.01, seed=97)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    psi_in = psi if prec == "fp64" else psi.astype(np.float32).astype(np.float64)
+    S = KronSolver(n, h, BCP, 12, omega)
+    W = vx_apply(psi_in[:no], g[:no], psi_in, S)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    psid = to_dev(psi_in, dt)
+    occ = to_dev(g[:no], torch.float64)
+    cache = tmp_path / "tune.txt"
+    for bits in (0, 1, 2, 3, 4):
+        plan = _forced_plan(kx, n, h, omega, prec, bits, 0, psid, occ, cache)
+        try:
+            vx = torch.zeros(psid.shape, dtype=torch.float64, device="cuda")
+            kx.exx_apply(plan, psid[:no], occ, psid, vx)
+            torch.cuda.synchronize()
+            err = rel_fro(to_host(vx), W)
+            assert err < tol, (bits, err)
+            if bits == 4:
+                plan2 = _forced_plan(kx, n, h, omega, prec, bits, 0, psid, occ, cache)
+                try:
+                    vxa = torch.zeros_like(vx)
+                    vxb = torch.zeros_like(vx)
+                    kx.exx_apply_batched([dict(plan=plan, psi=psid[:no], occ=occ, phi=psid, vx=vxa),
+                                          dict(plan=plan2, psi=psid[:no], occ=occ, phi=psid, vx=vxb)])
+                    torch.cuda.synchronize()
+                    assert kx.kx_batched_schedule()[3] == 2
+                    assert rel_fro(to_host(vxa), W) < tol
+                    assert rel_fro(to_host(vxb), W) < tol
+                finally:
+                    plan2.destroy()
+        finally:
+            plan.destroy()
