@@ -95,39 +95,49 @@ def run_form(kx, torch, cfg, psi_d, g_d, prec, path, steps, warmup, n_occ, autot
         torch.cuda.synchronize()
         kx.kx_trace_enable(True)
         stream = torch.cuda.current_stream()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(steps):
+        ev[0].record(stream)
+        for i in range(steps):
             kx.exx_apply(plan, psi[:n_occ], occ, psi, vx, ex=ex, gphi=g_d, path=path)
-        e1.record(stream)
+            ev[i + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        ms = e0.elapsed_time(e1)
+        ms = ev[0].elapsed_time(ev[steps])
+        per_step = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
         trace = kx.kx_trace_read()
         kx.kx_trace_enable(False)
         nt = plan.info()[7]
     finally:
         plan.destroy()
-    return dict(ms=ms, wall=wall, trace=trace, result=result, batch_targets=nt, tuning=tuning)
+    return dict(ms=ms, wall=wall, trace=trace, result=result, batch_targets=nt, tuning=tuning,
+                median_ms=per_step[len(per_step) // 2], min_ms=per_step[0])
 
 
 def cpu_baseline(cfg, psi, g, n_occ, bands):
-    """The oracle as it stands, single BLAS thread, on `bands` target bands."""
+    """The oracle as it stands on the host: BLAS threads = the cores this
+    process may use, on 4x `bands` target bands; and single-threaded on
+    `bands` target bands (whose result is returned for the accuracy check)."""
     from threadpoolctl import threadpool_limits
 
     from oracle.exx import vx_apply
     from oracle.kron import KronSolver
     S = KronSolver(cfg["n"], cfg["h"], cfg["bc"], cfg["order"], cfg["omega"])
+    cores = len(os.sched_getaffinity(0))
+    with threadpool_limits(cores):
+        t0 = time.perf_counter()
+        vx_apply(psi[:n_occ], g[:n_occ], psi[:4 * bands], S)
+        dt_all = time.perf_counter() - t0
     with threadpool_limits(1):
         t0 = time.perf_counter()
         W = vx_apply(psi[:n_occ], g[:n_occ], psi[:bands], S)
         dt = time.perf_counter() - t0
-    return W, dict(value=bands * n_occ / dt, unit="solves/s", cores=1, kind="oracle",
-                   sample=f"{bands} target bands x {n_occ} occupied = {bands * n_occ} pair solves "
-                          f"of the same workload, FP64 NumPy, 1 thread, {dt:.1f} s")
+    return W, dict(value=4 * bands * n_occ / dt_all, unit="solves/s", cores=cores, kind="oracle",
+                   sample=f"{4 * bands} target bands x {n_occ} occupied = {4 * bands * n_occ} pair solves "
+                          f"of the same workload, FP64 NumPy with {cores} BLAS threads, {dt_all:.1f} s",
+                   one_thread=dict(value=bands * n_occ / dt, cores=1,
+                                   sample=f"{bands} target bands x {n_occ} occupied, {dt:.1f} s"))
 
 
 def run_batched(kx, torch, np, cfg, args):
@@ -243,6 +253,36 @@ def run_batched(kx, torch, np, cfg, args):
     print(json.dumps(line), flush=True)
 
 
+def run_sweep(kx, torch, np, args):
+    """Time per Poisson solve against the number of right-hand sides per
+    kron_solve call (the batch size n_c of Sec. II.B), FP64 fused vs plain, on
+    periodic 50^3, 75^3, 100^3 grids (h = 0.3, screened kernel); one JSON line
+    per (grid, path, n_c)."""
+    rng = np.random.default_rng(7)
+    for n in (50, 75, 100):
+        plan = kx.kron_setup((n,) * 3, (0.3,) * 3, ("periodic",) * 3, 12, 0.106, prec="fp64")
+        try:
+            B = torch.from_numpy(rng.standard_normal((64, n ** 3))).cuda()
+            X = torch.empty_like(B)
+            for path in ("fused", "plain"):
+                for nc in (1, 2, 4, 8, 16, 20, 32, 64):
+                    for _ in range(3):
+                        kx.kron_solve(plan, B[:nc], X[:nc], path=path)
+                    torch.cuda.synchronize()
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(21)]
+                    ev[0].record()
+                    for i in range(20):
+                        kx.kron_solve(plan, B[:nc], X[:nc], path=path)
+                        ev[i + 1].record()
+                    torch.cuda.synchronize()
+                    t = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(20))
+                    print(json.dumps(dict(sweep="kron_solve", grid=[n] * 3, path=path, n_c=nc,
+                                          median_ms_per_call=round(t[10], 4), min_ms_per_call=round(t[0], 4),
+                                          median_us_per_solve=round(1e3 * t[10] / nc, 3))), flush=True)
+        finally:
+            plan.destroy()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +296,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch configuration instead of kx_autotune's choice")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line: time per solve vs right-hand sides per call")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB on the device first: a kernel of known traffic for scaling "
                          "FETCH_SIZE / WRITE_SIZE counters")
@@ -273,6 +315,9 @@ def main():
     from paper_2501_16572_amd.workloads import CONFIGS, make_inputs
 
     kx.load_library()
+    if args.sweep:
+        run_sweep(kx, torch, np, args)
+        return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -308,6 +353,7 @@ def main():
         t = r["ms"] / 1e3
         sps = solves * args.steps / t
         form = dict(solves_per_s=sps, ms_per_step=r["ms"] / args.steps,
+                    median_ms_per_step=round(r["median_ms"], 4), min_ms_per_step=round(r["min_ms"], 4),
                     useful_tflops=flops_per_solve * solves * args.steps / t / 1e12,
                     batch_targets=r["batch_targets"], tuning=r["tuning"],
                     kernels_ms={k: round(v[0] / args.steps, 4) for k, v in r["trace"].items()})
@@ -360,6 +406,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r["ms"] / args.steps, 4),
+        "median_ms_per_step": round(r["median_ms"], 4),
+        "min_ms_per_step": round(r["min_ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
