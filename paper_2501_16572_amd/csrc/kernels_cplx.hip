@@ -181,7 +181,18 @@ k_slice_fwd_c(SliceArgs a0, TaskTab tt) {
     const int PP = a.P * a.P;
     const int nk = (max(a.n1, a.n2) + 3) / 4;
     const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
-    const int p = (int)(item / a.n3), i3 = (int)(item - (int64_t)p * a.n3);
+    // pair-density items run target-fastest (as the FP64/FP32 kernel)
+    int p, i3;
+    if (IN == 0) {
+      const int n_t = a.npairs / a.n_occ;
+      const int64_t rest = item / n_t;
+      const int t = (int)(item - rest * n_t);
+      i3 = (int)(rest / a.n_occ);
+      p = t * a.n_occ + (int)(rest - (int64_t)i3 * a.n_occ);
+    } else {
+      p = (int)(item / a.n3);
+      i3 = (int)(item - (int64_t)p * a.n3);
+    }
     const int64_t soff = (int64_t)i3 * a.n12;
     const C2<T>* pa;
     const C2<T>* pb = nullptr;
@@ -372,7 +383,9 @@ k_slice_inv_c(AccArgs a0, TaskTab tt) {
     const int nk = (max(a.n1, a.n2) + 3) / 4;
     const unsigned m1 = 0xffffffffu / (unsigned)a.n1 + 1u;
     const int n_inner = ACC ? a.n_occ : 1;
-    const int u = (int)(item / a.n3), i3 = (int)(item - (int64_t)u * a.n3);
+    // items run target-fastest ((i3, u), u fastest)
+    const int nu = ACC ? a.n_t : a.n_t * a.n_occ;
+    const int i3 = (int)(item / nu), u = (int)(item - (int64_t)i3 * nu);
     const int64_t soff = (int64_t)i3 * a.n12;
     double wr[ACC ? NT : 1][4], wi[ACC ? NT : 1][4];
     if (ACC) {
