@@ -140,6 +140,36 @@ def cpu_baseline(cfg, psi, g, n_occ, bands):
                                    sample=f"{bands} target bands x {n_occ} occupied, {dt:.1f} s"))
 
 
+def run_ace(kx, torch, psi_d, w_d, dV, args):
+    """ACE from the FP64 Vx of all bands (Sec. III.A) and its application to
+    all bands (Sec. III.B), timed with HIP events; both are HBM-bound."""
+    n_s, N = psi_d.shape
+    work = torch.empty(kx.kx_ace_workspace_bytes(N, n_s, n_s, False) // 8 + 64, dtype=torch.float64,
+                       device="cuda")
+    xi = kx.ace_construct(psi_d, w_d, dV, work=work)
+    v = torch.zeros_like(psi_d)
+    kx.ace_apply(xi, psi_d, dV, v, work=work)
+    torch.cuda.synchronize()
+    err = float((v - w_d).norm() / w_d.norm())     # the operator reproduces W on the orbitals
+    reps = max(args.steps, 5)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        kx.ace_construct(psi_d, w_d, dV, xi=xi, work=work)
+    ev[1].record()
+    for _ in range(reps):
+        kx.ace_apply(xi, psi_d, dV, v, work=work)
+    ev[2].record()
+    torch.cuda.synchronize()
+    tc, ta = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
+    mat = N * n_s * 8
+    return dict(n_s=n_s, N=N, construct_ms=round(tc, 4), apply_ms=round(ta, 4),
+                construct_gbs=round(3 * mat / tc / 1e6, 1), apply_gbs=round(4 * mat / ta / 1e6, 1),
+                hbm_peak_gbs=8000.0, reproduces_w_rel_err=err,
+                note="algorithmic bytes: construct reads Psi, W and writes xi (3 N n_s 8 B); "
+                     "apply reads xi, Phi and reads+writes V Phi (4 N n_s 8 B)")
+
+
 def run_batched(kx, torch, np, cfg, args):
     """Several plans in one exx_apply_batched call (a k-point set with one
     Bloch plan per class of k - q, and Gamma-point systems of uneven sizes),
@@ -296,6 +326,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch configuration instead of kx_autotune's choice")
+    ap.add_argument("--no-ace", action="store_true", help="skip the ACE construction/application timing")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line: time per solve vs right-hand sides per call")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -373,6 +404,9 @@ def main():
             out_forms[k]["rel_err_vs_fp64_device"] = float((vx - ref_vx).norm() / ref_vx.norm())
             out_forms[k]["ex_err_per_atom_vs_fp64_device"] = abs(ex - ref_ex) / atoms
     head_vx, head_ex = results[f"{head[0]}_{head[1]}"]
+    ace = None
+    if "fp64_fused" in results and not args.no_ace:
+        ace = run_ace(kx, torch, psi_d, results["fp64_fused"][0], float(np.prod(cfg["h"])), args)
 
     prec, path, r, t = head
     # roofline of the dominant kernel of the headline form (fused passes)
@@ -424,6 +458,7 @@ def main():
         "forms": out_forms,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "ace": ace,
     }
     print(json.dumps(line), flush=True)
 

@@ -264,6 +264,37 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
  * i = A, B, C; out[6] = 1 if it came from kx_autotune (timed or cached). */
 kx_status kx_plan_tuning(kx_plan p, int out[7]);
 
+/* ---- Adaptively compressed exchange (ACE) --------------------------------
+ * FP64 (cplx = 0, real orbitals at Gamma) or complex128 (cplx = 1, interleaved
+ * (re, im)).  Orbital sets are column-major N x n (one orbital per column,
+ * leading dimension >= N); dV is the grid's volume element, so inner products
+ * are <a, b> = dV sum conj(a) b.  Every call is asynchronous on `stream` and
+ * needs a caller-owned device workspace (256-byte aligned) of at least
+ * kx_ace_workspace_bytes bytes; nothing is allocated.  Argument errors:
+ * KX_EINVAL before any device work. */
+
+/* kx_ace_workspace_bytes -- workspace for ace_construct (n_phi = 0) or
+ * ace_apply on n_phi trial orbitals, for N grid points and n_s orbitals
+ * (1 <= n_s <= 1024).  Host only. */
+kx_status kx_ace_workspace_bytes(int64_t N, int n_s, int n_phi, int cplx, int64_t* bytes);
+
+/* ace_construct -- the ACE operator of Sec. III.A from n_s orbitals Psi and
+ * W = Vx Psi (e.g. exx_apply with phi = Psi): M = dV Psi^H W (Hermitian,
+ * negative definite), -M = L L^H (lower Cholesky factor),
+ * xi = W L^{-H} (N x n_s, written to d_xi; the operator is -xi xi^H dV).
+ * d_info: one device int, set to 0, or to j+1 if the j-th pivot of -M is not
+ * positive (then d_xi is left unspecified); read it after synchronizing. */
+kx_status ace_construct(int64_t N, int n_s, int cplx, double dV, const void* d_psi, int64_t ld_psi,
+                        const void* d_w, int64_t ld_w, void* d_xi, int64_t ld_xi, void* d_work,
+                        int64_t work_bytes, int* d_info, void* stream);
+
+/* ace_apply -- the compressed operator on n_phi trial orbitals (Sec. III.B):
+ * chi = dV xi^H Phi (n_s x n_phi), then d_vphi += -xi chi (ACCUMULATES, like
+ * exx_apply).  n_phi = 0 is a no-op. */
+kx_status ace_apply(int64_t N, int n_s, int cplx, double dV, const void* d_xi, int64_t ld_xi,
+                    const void* d_phi, int64_t ld_phi, int n_phi, void* d_vphi, int64_t ld_vphi, void* d_work,
+                    int64_t work_bytes, void* stream);
+
 /* kx_last_error -- text for this thread's last non-OK status ("" if none).
  * The pointer stays valid until the next call on this thread. */
 const char* kx_last_error(void);

@@ -1301,6 +1301,96 @@ kx_status kx_workspace_bytes(kx_plan p, int n_b, int n_occ, int64_t* bytes) {
   return KX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// ACE construction and application
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kAceKc = 512;   // K rows per split-K chunk of the Gram products
+constexpr int kAceMaxNs = 1024;   // one workgroup factors / inverts the n_s x n_s matrix
+
+struct AceWork {
+  size_t part, small, total;
+};
+AceWork ace_work(int64_t N, int n_s, int n_phi, int cplx) {
+  const size_t eb = cplx ? 16 : 8;
+  const size_t chunks = (size_t)((N + kAceKc - 1) / kAceKc);
+  const size_t nmax = (size_t)std::max(n_s, n_phi);
+  AceWork w;
+  w.part = (chunks * (size_t)n_s * nmax * eb + 255) & ~(size_t)255;
+  w.small = ((3 * (size_t)n_s * n_s + (size_t)n_s * std::max(n_phi, 1)) * eb + 255) & ~(size_t)255;
+  w.total = w.part + w.small;
+  return w;
+}
+
+kx_status check_ace(int64_t N, int n_s, int cplx, const void* a, int64_t lda, const void* b, int64_t ldb,
+                    const void* c, int64_t ldc, const void* work, int64_t work_bytes, size_t need,
+                    const char* who) {
+  if (N <= 0 || n_s < 1 || n_s > kAceMaxNs)
+    return fail(KX_EINVAL, "%s: need N > 0 and 1 <= n_s <= %d", who, kAceMaxNs);
+  if (cplx != 0 && cplx != 1) return fail(KX_EINVAL, "%s: cplx must be 0 or 1", who);
+  if (!a || !b || !c || !work) return fail(KX_EINVAL, "%s: NULL pointer", who);
+  if (lda < N || ldb < N || ldc < N) return fail(KX_EINVAL, "%s: leading dimension below N", who);
+  const size_t eb = cplx ? 16 : 8;
+  if (((uintptr_t)a % eb) || ((uintptr_t)b % eb) || ((uintptr_t)c % eb) || ((uintptr_t)work % 256))
+    return fail(KX_EINVAL, "%s: misaligned pointer (work needs 256-byte alignment)", who);
+  if (work_bytes < 0 || (size_t)work_bytes < need)
+    return fail(KX_EINVAL, "%s: workspace of %lld bytes, %zu needed", who, (long long)work_bytes, need);
+  return KX_OK;
+}
+}  // namespace
+
+kx_status kx_ace_workspace_bytes(int64_t N, int n_s, int n_phi, int cplx, int64_t* bytes) {
+  if (!bytes) return fail(KX_EINVAL, "kx_ace_workspace_bytes: NULL argument");
+  if (N <= 0 || n_s < 1 || n_s > kAceMaxNs || n_phi < 0 || (cplx != 0 && cplx != 1))
+    return fail(KX_EINVAL, "kx_ace_workspace_bytes: bad sizes");
+  *bytes = (int64_t)ace_work(N, n_s, n_phi, cplx).total;
+  return KX_OK;
+}
+
+kx_status ace_construct(int64_t N, int n_s, int cplx, double dV, const void* d_psi, int64_t ld_psi,
+                        const void* d_w, int64_t ld_w, void* d_xi, int64_t ld_xi, void* d_work,
+                        int64_t work_bytes, int* d_info, void* stream) {
+  const AceWork aw = ace_work(N > 0 ? N : 1, n_s > 0 ? n_s : 1, 0, cplx == 1);
+  kx_status st = check_ace(N, n_s, cplx, d_psi, ld_psi, d_w, ld_w, d_xi, ld_xi, d_work, work_bytes, aw.total,
+                           "ace_construct");
+  if (st != KX_OK) return st;
+  if (!d_info) return fail(KX_EINVAL, "ace_construct: NULL info");
+  if (!(dV > 0.0)) return fail(KX_EINVAL, "ace_construct: dV must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t eb = cplx ? 16 : 8;
+  char* part = (char*)d_work;
+  char* S = part + aw.part;
+  char* U = S + (size_t)n_s * n_s * eb;
+  char* X = U + (size_t)n_s * n_s * eb;
+  // S = -M = -dV Psi^H W
+  hipError_t e = kx::launch_ace_gram(cplx, N, n_s, n_s, d_psi, ld_psi, d_w, ld_w, -dV, part, kAceKc, S, s);
+  if (e == hipSuccess) e = kx::launch_ace_potrf(cplx, n_s, S, d_info, s);
+  if (e == hipSuccess) e = kx::launch_ace_trtri(cplx, n_s, S, U, X, d_info, s);
+  if (e == hipSuccess) e = kx::launch_ace_tsmm(cplx, N, n_s, n_s, d_w, ld_w, U, 1.0, 0.0, d_xi, ld_xi, d_info, s);
+  if (e != hipSuccess) return dev_fail(e, "ace_construct launch");
+  return KX_OK;
+}
+
+kx_status ace_apply(int64_t N, int n_s, int cplx, double dV, const void* d_xi, int64_t ld_xi,
+                    const void* d_phi, int64_t ld_phi, int n_phi, void* d_vphi, int64_t ld_vphi, void* d_work,
+                    int64_t work_bytes, void* stream) {
+  if (n_phi < 0) return fail(KX_EINVAL, "ace_apply: negative n_phi");
+  if (n_phi == 0) return KX_OK;
+  const AceWork aw = ace_work(N > 0 ? N : 1, n_s > 0 ? n_s : 1, n_phi, cplx == 1);
+  kx_status st = check_ace(N, n_s, cplx, d_xi, ld_xi, d_phi, ld_phi, d_vphi, ld_vphi, d_work, work_bytes,
+                           aw.total, "ace_apply");
+  if (st != KX_OK) return st;
+  if (!(dV > 0.0)) return fail(KX_EINVAL, "ace_apply: dV must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  char* part = (char*)d_work;
+  char* chi = part + aw.part;
+  hipError_t e = kx::launch_ace_gram(cplx, N, n_s, n_phi, d_xi, ld_xi, d_phi, ld_phi, dV, part, kAceKc, chi, s);
+  if (e == hipSuccess)
+    e = kx::launch_ace_tsmm(cplx, N, n_s, n_phi, d_xi, ld_xi, chi, -1.0, 1.0, d_vphi, ld_vphi, nullptr, s);
+  if (e != hipSuccess) return dev_fail(e, "ace_apply launch");
+  return KX_OK;
+}
+
 kx_status kx_batched_schedule(int out[4]) {
   if (!out) return fail(KX_EINVAL, "kx_batched_schedule: NULL argument");
   std::lock_guard<std::mutex> lock(g_graph_mu);

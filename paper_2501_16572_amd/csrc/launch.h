@@ -77,6 +77,19 @@ hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks
 hipError_t launch_slice_inv_c(bool f64, int nk, int variant, const AccArgs& a, int64_t items,
                               int max_blocks, hipStream_t s, const TaskTab& tt = kNoTasks);
 
+// ACE kernels (kernels_ace.hip); cplx selects complex128, else FP64.
+//   gram:  C(m x n, ld m) = alpha * sum_k conj(A[k, i]) B[k, j] over K rows,
+//          split in chunks of kc rows; part holds ceil(K/kc) * m * n elements
+//   potrf: lower Cholesky factor of S (n x n) in place; *info = 0 or j+1
+//   trtri: U = L^{-H} (upper), X = L^{-1} scratch, both n x n; skipped if *info
+//   tsmm:  C(K x n) = beta C + alpha A(K x m) B(m x n, ld m); skipped if info && *info
+hipError_t launch_ace_gram(bool cplx, int64_t K, int m, int n, const void* A, int64_t lda, const void* B,
+                           int64_t ldb, double alpha, void* part, int64_t kc, void* C, hipStream_t s);
+hipError_t launch_ace_potrf(bool cplx, int n, void* S, int* info, hipStream_t s);
+hipError_t launch_ace_trtri(bool cplx, int n, const void* L, void* U, void* X, const int* info, hipStream_t s);
+hipError_t launch_ace_tsmm(bool cplx, int64_t K, int m, int n, const void* A, int64_t lda, const void* B,
+                           double alpha, double beta, void* C, int64_t ldc, const int* info, hipStream_t s);
+
 // Number of compute units of the current device (cached).
 int device_cu_count();
 

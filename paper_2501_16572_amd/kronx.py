@@ -33,7 +33,8 @@ FLAG_COMPLEX = 16
 EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_batched",
            "kx_plan_info", "kx_plan_tables", "kx_host_eig1d", "kx_host_fd_weights",
            "kx_last_error", "kx_trace_enable", "kx_trace_read", "kx_trace_name", "kx_autotune",
-           "kx_plan_tuning", "kx_batched_schedule", "kx_workspace_bytes"]
+           "kx_plan_tuning", "kx_batched_schedule", "kx_workspace_bytes", "kx_ace_workspace_bytes",
+           "ace_construct", "ace_apply"]
 
 
 class KronxError(RuntimeError):
@@ -84,6 +85,9 @@ def load_library(path=None):
     lib.kx_plan_tuning.argtypes = [vp, ip]
     lib.kx_batched_schedule.argtypes = [ip]
     lib.kx_workspace_bytes.argtypes = [vp, ci, ci, ctypes.POINTER(i64)]
+    lib.kx_ace_workspace_bytes.argtypes = [i64, ci, ci, ci, ctypes.POINTER(i64)]
+    lib.ace_construct.argtypes = [i64, ci, ci, cd, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp]
+    lib.ace_apply.argtypes = [i64, ci, ci, cd, vp, i64, vp, i64, ci, vp, i64, vp, i64, vp]
     for name in EXPORTS:
         if name not in ("kx_last_error", "kx_trace_name"):
             getattr(lib, name).restype = ci
@@ -261,6 +265,61 @@ def kx_workspace_bytes(plan, n_b, n_occ):
     _check(load_library().kx_workspace_bytes(plan.handle, n_b, n_occ, ctypes.byref(out)),
            "kx_workspace_bytes")
     return out.value
+
+
+def kx_ace_workspace_bytes(N, n_s, n_phi, cplx):
+    out = ctypes.c_int64(0)
+    _check(load_library().kx_ace_workspace_bytes(N, n_s, n_phi, 1 if cplx else 0, ctypes.byref(out)),
+           "kx_ace_workspace_bytes")
+    return out.value
+
+
+def _ace_work(N, n_s, n_phi, cplx, work):
+    import torch
+    need = kx_ace_workspace_bytes(N, n_s, n_phi, cplx)
+    if work is None or work.numel() * work.element_size() < need:
+        work = torch.empty(need // 8 + 64, dtype=torch.float64, device="cuda")
+    return work
+
+
+def ace_construct(psi, w, dV, xi=None, work=None, stream=None):
+    """xi (n_s, N) of the ACE operator from psi and w = Vx psi (both (n_s, N),
+    float64 or complex128, CUDA).  Raises if -dV psi^H w is not positive definite."""
+    import torch
+    n_s, N = psi.shape
+    cplx = psi.is_complex()
+    if xi is None:
+        xi = torch.empty_like(w)
+    pp, ldp = _cols(psi, N, "psi")
+    pw, ldw = _cols(w, N, "w")
+    px, ldx = _cols(xi, N, "xi")
+    work = _ace_work(N, n_s, 0, cplx, work)
+    info = torch.zeros(1, dtype=torch.int32, device=psi.device)
+    st = load_library().ace_construct(N, n_s, 1 if cplx else 0, float(dV), ctypes.c_void_p(pp), ldp,
+                                      ctypes.c_void_p(pw), ldw, ctypes.c_void_p(px), ldx,
+                                      ctypes.c_void_p(work.data_ptr()),
+                                      work.numel() * work.element_size(),
+                                      ctypes.c_void_p(info.data_ptr()), _stream(stream))
+    _check(st, "ace_construct")
+    if int(info.item()) != 0:
+        raise KronxError(KX_EINVAL, "ace_construct", f"-M not positive definite at pivot {int(info.item())}")
+    return xi
+
+
+def ace_apply(xi, phi, dV, vphi, work=None, stream=None):
+    """vphi += -xi (dV xi^H phi); xi (n_s, N), phi and vphi (n_phi, N)."""
+    n_s, N = xi.shape
+    cplx = xi.is_complex()
+    px, ldx = _cols(xi, N, "xi")
+    pf, ldf = _cols(phi, N, "phi")
+    pv, ldv = _cols(vphi, N, "vphi")
+    work = _ace_work(N, n_s, phi.shape[0], cplx, work)
+    st = load_library().ace_apply(N, n_s, 1 if cplx else 0, float(dV), ctypes.c_void_p(px), ldx,
+                                  ctypes.c_void_p(pf), ldf, phi.shape[0], ctypes.c_void_p(pv), ldv,
+                                  ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size(),
+                                  _stream(stream))
+    _check(st, "ace_apply")
+    return vphi
 
 
 def kx_batched_schedule():

@@ -97,3 +97,26 @@ def test_null_plan_errors():
     assert lib.exx_apply_batched(None, -1, None) == kronx.KX_EINVAL
     assert lib.kx_host_eig1d(0, 0.3, 0, 12, 0.0, None, None, None) == kronx.KX_EINVAL
     assert lib.kx_host_fd_weights(5, None) == kronx.KX_EINVAL
+
+
+def test_ace_workspace_size_and_argument_errors():
+    # host-only: the workspace formula (split-K partials of 512-row chunks,
+    # 256-byte aligned, plus the small n_s x n_s matrices) and EINVAL before
+    # any device work
+    N, ns = 373248, 128
+    chunks = -(-N // 512)
+    part = chunks * ns * ns * 8
+    small = (3 * ns * ns + ns) * 8
+    align = lambda b: (b + 255) // 256 * 256
+    assert kronx.kx_ace_workspace_bytes(N, ns, 0, False) == align(part) + align(small)
+    assert kronx.kx_ace_workspace_bytes(N, ns, 200, True) == align(chunks * ns * 200 * 16) + align(
+        (3 * ns * ns + ns * 200) * 16)
+    lib = kronx.load_library()
+    for bad in [(0, 4), (100, 0), (100, 1025)]:
+        out = ctypes.c_int64(0)
+        assert lib.kx_ace_workspace_bytes(bad[0], bad[1], 0, 0, ctypes.byref(out)) == kronx.KX_EINVAL
+    st = lib.ace_construct(1000, 4, 0, 1.0, None, 1000, None, 1000, None, 1000, None, 0, None, None)
+    assert st == kronx.KX_EINVAL
+    assert "NULL" in kronx.kx_last_error() or "need" in kronx.kx_last_error()
+    st = lib.ace_apply(1000, 4, 0, 1.0, None, 1000, None, 1000, 0, None, 1000, None, 0, None)
+    assert st == kronx.KX_OK  # n_phi = 0: no-op
