@@ -1305,18 +1305,19 @@ kx_status kx_workspace_bytes(kx_plan p, int n_b, int n_occ, int64_t* bytes) {
 // ACE construction and application
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int64_t kAceKc = 512;   // K rows per split-K chunk of the Gram products
 constexpr int kAceMaxNs = 1024;   // one workgroup factors / inverts the n_s x n_s matrix
 
 struct AceWork {
   size_t part, small, total;
 };
+// One workspace serves ace_construct (Gram n_s x n_s) and ace_apply (Gram
+// n_s x n_phi) for the same sizes.
 AceWork ace_work(int64_t N, int n_s, int n_phi, int cplx) {
   const size_t eb = cplx ? 16 : 8;
-  const size_t chunks = (size_t)((N + kAceKc - 1) / kAceKc);
-  const size_t nmax = (size_t)std::max(n_s, n_phi);
+  const size_t pc = (size_t)kx::ace_gram_part_bytes(cplx, N, n_s, n_s);
+  const size_t pa = n_phi > 0 ? (size_t)kx::ace_gram_part_bytes(cplx, N, n_s, n_phi) : 0;
   AceWork w;
-  w.part = (chunks * (size_t)n_s * nmax * eb + 255) & ~(size_t)255;
+  w.part = (std::max(pc, pa) + 255) & ~(size_t)255;
   w.small = ((3 * (size_t)n_s * n_s + (size_t)n_s * std::max(n_phi, 1)) * eb + 255) & ~(size_t)255;
   w.total = w.part + w.small;
   return w;
@@ -1363,9 +1364,9 @@ kx_status ace_construct(int64_t N, int n_s, int cplx, double dV, const void* d_p
   char* U = S + (size_t)n_s * n_s * eb;
   char* X = U + (size_t)n_s * n_s * eb;
   // S = -M = -dV Psi^H W
-  hipError_t e = kx::launch_ace_gram(cplx, N, n_s, n_s, d_psi, ld_psi, d_w, ld_w, -dV, part, kAceKc, S, s);
-  if (e == hipSuccess) e = kx::launch_ace_potrf(cplx, n_s, S, d_info, s);
-  if (e == hipSuccess) e = kx::launch_ace_trtri(cplx, n_s, S, U, X, d_info, s);
+  hipError_t e = kx::launch_ace_gram(cplx, N, n_s, n_s, d_psi, ld_psi, d_w, ld_w, -dV, part, S, s);
+  // -M = L L^H, U = L^{-H}
+  if (e == hipSuccess) e = kx::launch_ace_factor(cplx, n_s, S, U, X, d_info, s);
   if (e == hipSuccess) e = kx::launch_ace_tsmm(cplx, N, n_s, n_s, d_w, ld_w, U, 1.0, 0.0, d_xi, ld_xi, d_info, s);
   if (e != hipSuccess) return dev_fail(e, "ace_construct launch");
   return KX_OK;
@@ -1384,7 +1385,7 @@ kx_status ace_apply(int64_t N, int n_s, int cplx, double dV, const void* d_xi, i
   hipStream_t s = (hipStream_t)stream;
   char* part = (char*)d_work;
   char* chi = part + aw.part;
-  hipError_t e = kx::launch_ace_gram(cplx, N, n_s, n_phi, d_xi, ld_xi, d_phi, ld_phi, dV, part, kAceKc, chi, s);
+  hipError_t e = kx::launch_ace_gram(cplx, N, n_s, n_phi, d_xi, ld_xi, d_phi, ld_phi, dV, part, chi, s);
   if (e == hipSuccess)
     e = kx::launch_ace_tsmm(cplx, N, n_s, n_phi, d_xi, ld_xi, chi, -1.0, 1.0, d_vphi, ld_vphi, nullptr, s);
   if (e != hipSuccess) return dev_fail(e, "ace_apply launch");

@@ -6,14 +6,15 @@
 // column, leading dimension ld >= N); the small matrices are column-major with
 // leading dimension equal to their row count.
 //
-// The two products with the long dimension N are bound by HBM traffic (each
-// reads tall matrices once or twice); they are tiled FP64 VALU kernels:
+// The two products with the long dimension N are FP64 contractions of 2 n^2
+// flops per grid point against 16 n bytes, so for n_s of order 100 they are
+// bound by the FP64 matrix units rather than HBM; both run on MFMA:
 //   gram:  C(m x n) = alpha * sum_k conj(A[k, i]) B[k, j], split over K in
 //          chunks whose partial tiles are summed in a fixed order (bitwise
 //          reproducible results);
 //   tsmm:  C(K x n) = beta * C + alpha * A(K x m) B(m x n).
 // The Cholesky factorization and the triangular inverse of the n_s x n_s
-// matrix run in one workgroup each.
+// matrix run in one workgroup, in LDS where the matrix fits.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -66,80 +67,6 @@ constexpr int TB = 64;   // output tile edge
 constexpr int KB = 32;   // K rows staged per step
 constexpr int THR = 256; // 16 x 16 threads, 4 x 4 outputs each
 
-// Partial Gram tiles: part[c][i + j*m] = sum over rows k of chunk c of
-// conj(A[k + i*lda]) B[k + j*ldb].  grid = (chunks, tiles over m, tiles over n).
-template <typename T>
-__global__ void __launch_bounds__(THR) k_gram_partial(int64_t K, int m, int n, const T* __restrict__ A,
-                                                      int64_t lda, const T* __restrict__ B, int64_t ldb,
-                                                      T* __restrict__ part, int64_t kc) {
-  __shared__ T As[KB][TB + 1], Bs[KB][TB + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int64_t k0 = (int64_t)blockIdx.x * kc, k1 = min(K, k0 + kc);
-  const int i0 = blockIdx.y * TB, j0 = blockIdx.z * TB;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = zero_<T>();
-  // rows ks .. ks+KB-1 of the block's 64 columns of A and B, loaded into
-  // registers one step ahead of the LDS tile being consumed
-  constexpr int EPT = TB * KB / THR;
-  T ra[EPT], rb[EPT];
-  auto fetch = [&](int64_t ks) {
-#pragma unroll
-    for (int r = 0; r < EPT; ++r) {
-      const int e = tid + r * THR, kk = e % KB, c = e / KB;
-      const int64_t k = ks + kk;
-      ra[r] = (k < k1 && i0 + c < m) ? A[k + (int64_t)(i0 + c) * lda] : zero_<T>();
-      rb[r] = (k < k1 && j0 + c < n) ? B[k + (int64_t)(j0 + c) * ldb] : zero_<T>();
-    }
-  };
-  fetch(k0);
-  for (int64_t ks = k0; ks < k1; ks += KB) {
-#pragma unroll
-    for (int r = 0; r < EPT; ++r) {
-      const int e = tid + r * THR, kk = e % KB, c = e / KB;
-      As[kk][c] = ra[r];
-      Bs[kk][c] = rb[r];
-    }
-    __syncthreads();
-    if (ks + KB < k1) fetch(ks + KB);
-#pragma unroll 4
-    for (int kk = 0; kk < KB; ++kk) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = conj_(As[kk][tx + 16 * a]);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][ty + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma_(av[a], bv[b], acc[a][b]);
-    }
-    __syncthreads();
-  }
-  T* out = part + (int64_t)blockIdx.x * m * n;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
-      if (i < m && j < n) out[i + (int64_t)j * m] = acc[a][b];
-    }
-}
-
-// C[i + j*m] = alpha * sum_c part[c][i + j*m], chunks summed in order.
-template <typename T>
-__global__ void k_gram_reduce(int chunks, int m, int n, const T* __restrict__ part, double alpha,
-                              T* __restrict__ C) {
-  const int64_t mn = (int64_t)m * n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
-    T s = zero_<T>();
-    for (int c = 0; c < chunks; ++c) s = add_(s, part[c * mn + e]);
-    C[e] = scale_(alpha, s);
-  }
-}
-
 // In-place lower Cholesky factor of the Hermitian positive definite n x n
 // matrix S (column-major, ld n): S = L L^H, L overwrites the lower triangle.
 // One workgroup; *info = 0, or j+1 if the j-th pivot is not positive (then
@@ -180,68 +107,6 @@ __global__ void __launch_bounds__(1024) k_potrf_lower(int n, T* S, int* info) {
     __syncthreads();
   }
   if (tid == 0) *info = bad;
-}
-
-// The same two factorizations with the working matrix in LDS (n <= NMAX):
-// the serial chains of the column steps then run on LDS latency instead of
-// global-memory latency.
-template <typename T, int NMAX>
-__global__ void __launch_bounds__(1024) k_potrf_lower_lds(int n, T* S, int* info) {
-  __shared__ T A[NMAX * NMAX];
-  __shared__ double red[32];
-  __shared__ int bad;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int e = tid; e < n * n; e += nthr) A[e] = S[e];
-  if (tid == 0) bad = 0;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    double part = 0.0;
-    for (int k = tid; k < j; k += nthr) part += abs2_(A[j + k * n]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = part;
-    __syncthreads();
-    if (tid == 0) {
-      double sum = 0.0;
-      for (int w = 0; w < (nthr + 63) / 64; ++w) sum += red[w];
-      const double d = real_(A[j + j * n]) - sum;
-      if (!(d > 0.0)) bad = j + 1;
-      else A[j + j * n] = from_real_(sqrt(d), zero_<T>());
-    }
-    __syncthreads();
-    if (bad) break;
-    const double inv = 1.0 / real_(A[j + j * n]);
-    for (int i = j + 1 + tid; i < n; i += nthr) {
-      T sum = A[i + j * n];
-      for (int k = 0; k < j; ++k) sum = sub_(sum, mul_(A[i + k * n], conj_(A[j + k * n])));
-      A[i + j * n] = scale_(inv, sum);
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < n * n; e += nthr) S[e] = A[e];
-  if (tid == 0) *info = bad;
-}
-
-// U = L^{-H} with X = L^{-1} in LDS (row-major, so the threads of a row read
-// consecutive words): rows of X in order, the columns of a row in parallel (thread j: X[i][j] = (delta_ij - sum_{j<=k<i} L[i][k] X[k][j]) / L[i][i]).
-template <typename T, int NMAX>
-__global__ void __launch_bounds__(1024) k_trtri_lower_ch_lds(int n, const T* L, T* U, const int* info) {
-  if (*info) return;
-  __shared__ T X[NMAX * NMAX];
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int i = 0; i < n; ++i) {
-    const double inv = 1.0 / real_(L[i + (int64_t)i * n]);
-    for (int j = tid; j <= i; j += nthr) {
-      T sum = (i == j) ? one_<T>() : zero_<T>();
-      for (int k = j; k < i; ++k) sum = sub_(sum, mul_(L[i + (int64_t)k * n], X[k * n + j]));
-      X[i * n + j] = scale_(inv, sum);
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < n * n; e += nthr) {
-    const int i = e % n, j = e / n;  // U[i][j] = conj(X[j][i]) for j >= i
-    U[e] = (j >= i) ? conj_(X[j * n + i]) : zero_<T>();
-  }
 }
 
 // U = L^{-H} (upper triangular, column-major, ld n) from the lower factor L
@@ -324,74 +189,538 @@ __global__ void __launch_bounds__(THR) k_tsmm(int64_t K, int m, int n, const T* 
     }
 }
 
-template <typename T>
-hipError_t gram(int64_t K, int m, int n, const void* A, int64_t lda, const void* B, int64_t ldb, double alpha,
-                void* part, int64_t kc, void* C, hipStream_t s) {
-  if (K <= 0 || m <= 0 || n <= 0) return hipSuccess;
-  const int chunks = (int)((K + kc - 1) / kc);
-  dim3 grid(chunks, (m + TB - 1) / TB, (n + TB - 1) / TB);
-  hipLaunchKernelGGL(k_gram_partial<T>, grid, dim3(THR), 0, s, K, m, n, (const T*)A, lda, (const T*)B, ldb,
-                     (T*)part, kc);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t mn = (int64_t)m * n;
-  const int blocks = (int)std::min<int64_t>((mn + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_gram_reduce<T>, dim3(blocks), dim3(256), 0, s, chunks, m, n, (const T*)part, alpha, (T*)C);
-  return hipGetLastError();
+// ---------------------------------------------------------------------------
+// MFMA forms (v_mfma_f64_16x16x4).  Operand layout, lane l = 16*lg + lr:
+// A fragment A[row = lr][k = lg], B fragment B[k = lg][col = lr], accumulator
+// element r at D[row = lg + 4*r][col = lr].
+//
+// Complex operands are read as doubles (re, im interleaved), so that a complex
+// product becomes two real contractions over twice the length:
+//   Re(conj(a) b) = ar br + ai bi     = sum_q a_q b_q
+//   Im(conj(a) b) = ar bi - ai br     = sum_q a_q bt_q,  bt_{2c} = b_{2c+1}, bt_{2c+1} = -b_{2c}
+// and for the tall-skinny product C = A B (no conjugate):
+//   Re(a b) = ar br - ai bi = sum_q a_q x_q,   x_{2c} = br, x_{2c+1} = -bi
+//   Im(a b) = ar bi + ai br = sum_q a_q xt_q,  xt_{2c} = bi, xt_{2c+1} = br
+// ---------------------------------------------------------------------------
+typedef double d4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+constexpr int GKB = 64;           // rows (doubles) of A and B staged per step
+constexpr int GP = GKB + 2;       // LDS pitch (2 mod 32): conflict-free fragment reads
+constexpr int GTILE = 128 * 128;  // doubles of one output tile's partial
+
+// Partial Gram tiles, split over K (in doubles: K2 = K or 2K).  A block of
+// four waves owns one output tile (128 x 128 real, 128 x 64 complex with
+// separate Re / Im accumulators) and one chunk of rows; wave w computes a
+// 64-row x (64 | 32)-column quadrant.  Partials are stored in accumulator
+// order (every store is a contiguous 512-byte wave line); k_gram_mfma_reduce
+// maps them back to (i, j).
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_gram_mfma(int64_t K2, int m, int n, const double* __restrict__ A,
+                                                   int64_t lda2, const double* __restrict__ B, int64_t ldb2,
+                                                   double* __restrict__ part, int64_t kc2) {
+  constexpr int BN = CPLX ? 64 : 128, WN = BN / 2, NTJ = WN / 16, SETS = CPLX ? 2 : 1;
+  constexpr int LA = 128 * GKB / 256, LB = BN * GKB / 256;
+  __shared__ double As[128 * GP], Bs[BN * GP];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
+  const int wm = w & 1, wn = w >> 1;
+  const int64_t k0 = (int64_t)blockIdx.x * kc2, k1 = min(K2, k0 + kc2);
+  const int i0 = blockIdx.y * 128, j0 = blockIdx.z * BN;
+  d4_t acc[SETS][4][NTJ];
+#pragma unroll
+  for (int st = 0; st < SETS; ++st)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < NTJ; ++b) acc[st][a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+  // Loads are unconditional (row and column indices clamped into the
+  // matrices) so that no branch separates them from the MFMA loop; rows past
+  // the chunk and columns past m / n are zeroed when the slab goes to LDS.
+  double ra[LA], rb[LB];
+  auto fetch = [&](int64_t ks) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + 256 * r, c = min(i0 + e / GKB, m - 1);
+      const int64_t k = min(ks + e % GKB, K2 - 1);
+      ra[r] = A[k + (int64_t)c * lda2];
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + 256 * r, c = min(j0 + e / GKB, n - 1);
+      const int64_t k = min(ks + e % GKB, K2 - 1);
+      rb[r] = B[k + (int64_t)c * ldb2];
+    }
+  };
+  fetch(k0);
+  for (int64_t ks = k0; ks < k1; ks += GKB) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = tid + 256 * r;
+      const bool ok = ks + e % GKB < k1 && i0 + e / GKB < m;
+      As[(e / GKB) * GP + e % GKB] = ok ? ra[r] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = tid + 256 * r;
+      const bool ok = ks + e % GKB < k1 && j0 + e / GKB < n;
+      Bs[(e / GKB) * GP + e % GKB] = ok ? rb[r] : 0.0;
+    }
+    __syncthreads();
+    if (ks + GKB < k1) fetch(ks + GKB);
+#pragma unroll
+    for (int s4 = 0; s4 < GKB / 4; ++s4) {
+      const int kk = 4 * s4 + lg;
+      double av[4], bv[NTJ], bt[NTJ];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[(wm * 64 + 16 * a + lr) * GP + kk];
+#pragma unroll
+      for (int b = 0; b < NTJ; ++b) {
+        const double* col = Bs + (wn * WN + 16 * b + lr) * GP;
+        bv[b] = col[kk];
+        if (CPLX) bt[b] = (lg & 1) ? -col[kk - 1] : col[kk + 1];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < NTJ; ++b) {
+          acc[0][a][b] = mfma64(av[a], bv[b], acc[0][a][b]);
+          if (CPLX) acc[SETS - 1][a][b] = mfma64(av[a], bt[b], acc[SETS - 1][a][b]);
+        }
+    }
+    __syncthreads();
+  }
+  // partial of this chunk and tile, in accumulator order
+  const int64_t tile = (int64_t)blockIdx.y * gridDim.z + blockIdx.z;
+  double* out = part + ((int64_t)blockIdx.x * gridDim.y * gridDim.z + tile) * GTILE;
+#pragma unroll
+  for (int st = 0; st < SETS; ++st)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < NTJ; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out[((((w * SETS + st) * 4 + a) * NTJ + b) * 4 + r) * 64 + lane] = acc[st][a][b][r];
+}
+
+// C[i + j*m] = alpha * sum_c partial_c(i, j), the chunks summed in a fixed
+// order: block = 64 consecutive partial entries x 4 waves; wave g sums chunks
+// g, g+4, ... and the four sums are added in wave order.
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_gram_mfma_reduce(int chunks, int tiles_n, int64_t per_chunk, int m,
+                                                          int n, const double* __restrict__ part, double alpha,
+                                                          double* __restrict__ C) {
+  constexpr int BN = CPLX ? 64 : 128, WN = BN / 2, NTJ = WN / 16, SETS = CPLX ? 2 : 1;
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  double s = 0.0;
+#pragma unroll 8
+  for (int c = g; c < chunks; c += 4) s += part[(int64_t)c * per_chunk + e];
+  red[g][lane] = s;
+  __syncthreads();
+  if (g != 0) return;
+  s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  // decode (tile, w, set, a, b, r, lane) of the accumulator-order index
+  const int64_t tile = e / GTILE;
+  int q = (int)(e % GTILE);
+  const int l = q & 63;
+  q >>= 6;
+  const int r = q & 3;
+  q >>= 2;
+  const int b = q % NTJ;
+  q /= NTJ;
+  const int a = q & 3;
+  q >>= 2;
+  const int st = q % SETS, w = q / SETS;
+  const int i = (int)(tile / tiles_n) * 128 + (w & 1) * 64 + 16 * a + (l >> 4) + 4 * r;
+  const int j = (int)(tile % tiles_n) * BN + (w >> 1) * WN + 16 * b + (l & 15);
+  if (i < m && j < n) C[(i + (int64_t)j * m) * SETS + st] = alpha * s;
+}
+
+// C(K x n) = beta C + alpha A(K x m) B(m x n) for m <= 128, computed as
+// C^T = B^T A^T so that each accumulator row is a run of 16 consecutive rows
+// of C (whole cache lines per store).  B (its n-tile of 128 real / 64 complex
+// columns) stays in LDS for the whole launch; A is read straight from global
+// memory into fragment registers, one group of 8 steps ahead.  Each wave owns
+// 32-row tiles of C, taken in a grid stride.  Skipped when info && *info.
+constexpr int TQ = 258;  // LDS pitch (doubles) of the B tile: 2 mod 32
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, const double* __restrict__ A,
+                                                   int64_t lda, const double* __restrict__ B, double alpha,
+                                                   double beta, double* C, int64_t ldc, const int* info) {
+  if (info && *info) return;
+  constexpr int NJ = CPLX ? 64 : 128, NTJ = 4, SETS = CPLX ? 2 : 1, G = 8;
+  constexpr int PITCH = CPLX ? TQ : 130;
+  __shared__ double Xs[NJ * PITCH];
+  const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int Q = CPLX ? 2 * m : m;  // contraction length in doubles
+  const int QS = (Q + 3) / 4;      // 4-deep steps (the last group may run past QS)
+  const int j0 = blockIdx.y * NJ;
+  // X[j][q] = B as doubles: column j of B is contiguous in q
+  for (int e = tid; e < NJ * PITCH; e += 256) {
+    const int j = e / PITCH, q = e % PITCH;
+    Xs[e] = (q < Q && j0 + j < n) ? B[q + (int64_t)(j0 + j) * Q] : 0.0;
+  }
+  __syncthreads();
+  const int tiles = (int)((K + 31) / 32);
+  const int wstride = gridDim.x * 4;
+  // real: the wave covers all 128 columns in 8 tiles, one set; complex: 64
+  // columns in 4 tiles, two sets (Re, Im)
+  constexpr int TJ = CPLX ? 4 : 8;
+  d4_t acc[SETS][TJ][2];
+  double y[2][G], yn[2][G];
+  const int ngroups = (QS + G - 1) / G;
+  // Unconditional loads with clamped indices, so that no branch separates
+  // them from the MFMA loop: rows past K produce results that are not stored,
+  // contraction indices past Q meet zero rows of X.
+  auto load = [&](double (&dst)[2][G], int tile, int grp) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int64_t k = min((int64_t)tile * 32 + 16 * t + lr, K - 1);
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int q = 4 * (grp * G + u) + lg;
+        if (CPLX) {
+          // q = 2c + p: A[k, c] part p
+          const int c = min(q >> 1, m - 1);
+          dst[t][u] = A[2 * (k + (int64_t)c * lda) + (q & 1)];
+        } else {
+          const int c = min(q, m - 1);
+          dst[t][u] = A[k + (int64_t)c * lda];
+        }
+      }
+    }
+  };
+  int tile = blockIdx.x * 4 + w;
+  if (tile >= tiles) return;
+  load(y, tile, 0);
+  for (;;) {
+#pragma unroll
+    for (int st = 0; st < SETS; ++st)
+#pragma unroll
+      for (int a = 0; a < TJ; ++a)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[st][a][t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int grp = 0; grp < ngroups; ++grp) {
+      // prefetch the next group of this wave's sequence (past the last tile:
+      // a clamped, harmless reload of the last one)
+      const bool last = grp + 1 == ngroups;
+      load(yn, last ? min(tile + wstride, tiles - 1) : tile, last ? 0 : grp + 1);
+      // steps past QS read zero rows of X (staged up to the padded pitch)
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int q = 4 * (grp * G + u) + lg;
+        double x0[TJ], x1[TJ];
+#pragma unroll
+        for (int a = 0; a < TJ; ++a) {
+          const double* row = Xs + (16 * a + lr) * PITCH;
+          if (CPLX) {
+            const double ev = row[q & ~1], od = row[q | 1];
+            x0[a] = (lg & 1) ? -od : ev;  // Re: (br, -bi)
+            x1[a] = (lg & 1) ? ev : od;   // Im: (bi, br)
+          } else {
+            x0[a] = row[q];
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < TJ; ++a)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            acc[0][a][t] = mfma64(x0[a], y[t][u], acc[0][a][t]);
+            if (CPLX) acc[SETS - 1][a][t] = mfma64(x1[a], y[t][u], acc[SETS - 1][a][t]);
+          }
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < G; ++u) y[t][u] = yn[t][u];
+    }
+    // tile done: D[j][k], j = j0 + 16a + lg + 4r, k = 32 tile + 16t + lr.
+    // With beta != 0 the old values of C are loaded for two j-tiles at a
+    // time before any of them is stored (a load after a store to C cannot
+    // be hoisted by the compiler, which would serialize every update).
+#pragma unroll
+    for (int a0 = 0; a0 < TJ; a0 += 2) {
+      double old[2][2][4][SETS];
+      if (beta != 0.0) {
+#pragma unroll
+        for (int da = 0; da < 2; ++da)
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int j = min(j0 + 16 * (a0 + da) + lg + 4 * r, n - 1);
+              const int64_t k = min((int64_t)tile * 32 + 16 * t + lr, K - 1);
+#pragma unroll
+              for (int st = 0; st < SETS; ++st) old[da][t][r][st] = C[(k + (int64_t)j * ldc) * SETS + st];
+            }
+      }
+#pragma unroll
+      for (int da = 0; da < 2; ++da)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = j0 + 16 * (a0 + da) + lg + 4 * r;
+            const int64_t k = (int64_t)tile * 32 + 16 * t + lr;
+            if (k < K && j < n) {
+#pragma unroll
+              for (int st = 0; st < SETS; ++st) {
+                double v = alpha * acc[st][a0 + da][t][r];
+                if (beta != 0.0) v += beta * old[da][t][r][st];
+                C[(k + (int64_t)j * ldc) * SETS + st] = v;
+              }
+            }
+          }
+    }
+    tile += wstride;
+    if (tile >= tiles) break;
+  }
+}
+
+// Cholesky factor and triangular inverse of the n x n Hermitian matrix S
+// (n <= 128) in one workgroup of 1024 threads, the matrix held in registers:
+// thread (row = tid % 128, grp = tid / 128) keeps the 16 elements of row
+// `row` in columns grp, grp + 8, ..., grp + 120.  Each column step publishes
+// one column through a small LDS vector (double-buffered, so one barrier per
+// factorization step); the matrix itself never goes through LDS.
+//
+// Factorization, right-looking without square roots inside the loop: step j
+// subtracts A_ij conj(A_kj) / A_jj from the trailing triangle (j < k <= i);
+// afterwards l_ij = A_ij / sqrt(A_jj), l_jj = sqrt(A_jj).
+// Inverse, in place, columns right to left (X_22 = inverse of the trailing
+// block, already in place):
+//   x_jj = 1/l_jj,  x_(j+1:, j) = -X_22 l_(j+1:, j) / l_jj,
+// the products split over the 8 groups and summed in group order.
+// Writes U = L^{-H} = X^H (upper, ld n) and *info: 0, or j+1 at the first
+// non-positive pivot (U then left untouched).
+template <typename T>
+__global__ void __launch_bounds__(1024) k_chol_inv_reg(int n, const T* __restrict__ S, T* __restrict__ U,
+                                                       int* info) {
+  constexpr int KT = 16;
+  __shared__ T col[2][128];
+  __shared__ T red[8][128];
+  const int tid = threadIdx.x, i = tid & 127, grp = tid >> 7;
+  const bool live = i < n;
+  T a[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int k = grp + 8 * t;
+    a[t] = zero_<T>();
+    if (live && k < n) a[t] = S[i + (int64_t)k * n];
+  }
+  // Slot t holds column block (t + R) mod 16 (column j = 8 * block + grp).
+  // The block being eliminated is kept in slot 0 by rotating the slots once
+  // per block, so that every slot index is a compile-time constant (a runtime
+  // index would move `a` to scratch memory).
+  auto rot_left = [&]() {  // R += 1
+    const T f = a[0];
+#pragma unroll
+    for (int t = 0; t < KT - 1; ++t) a[t] = a[t + 1];
+    a[KT - 1] = f;
+  };
+  auto rot_right = [&]() {  // R -= 1
+    const T l = a[KT - 1];
+#pragma unroll
+    for (int t = KT - 1; t > 0; --t) a[t] = a[t - 1];
+    a[0] = l;
+  };
+  const int nblk = (n + 7) / 8;
+  int bad = 0, buf = 0;
+  for (int jb = 0; jb < nblk && !bad; ++jb) {  // R = jb here
+    for (int jr = 0; jr < 8; ++jr) {
+      const int j = 8 * jb + jr;
+      if (j >= n) break;
+      if (grp == jr && live && i >= j) col[buf][i] = a[0];
+      __syncthreads();
+      const double d = real_(col[buf][j]);
+      if (!(d > 0.0)) {  // every thread reads the same value: a uniform exit
+        bad = j + 1;
+        break;
+      }
+      if (live && i > j) {
+        const T lij = scale_(1.0 / d, col[buf][i]);
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+          const int k = grp + 8 * ((t + jb) & (KT - 1));
+          if (k > j && k <= i) a[t] = sub_(a[t], mul_(lij, conj_(col[buf][k])));
+        }
+      }
+      buf ^= 1;
+    }
+    rot_left();
+  }
+  if (bad) {
+    if (tid == 0) *info = bad;
+    return;
+  }
+  int R = nblk & (KT - 1);
+  // l_ij = A_ij / sqrt(A_jj): publish the pivots, then scale
+#pragma unroll
+  for (int t = 0; t < KT; ++t)
+    if (live && grp + 8 * ((t + R) & (KT - 1)) == i) red[0][i] = a[t];
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int k = grp + 8 * ((t + R) & (KT - 1));
+    if (live && k <= i) {
+      const double sd = sqrt(real_(red[0][k]));
+      if (k == i) a[t] = from_real_(sd, zero_<T>());
+      else a[t] = scale_(1.0 / sd, a[t]);
+    }
+  }
+  __syncthreads();
+  // in-place inverse, columns right to left, the current block in slot 0
+  for (int jb = nblk - 1; jb >= 0; --jb) {
+    rot_right();  // R = jb
+    for (int jr = 7; jr >= 0; --jr) {
+      const int j = 8 * jb + jr;
+      if (j >= n) continue;
+      if (grp == jr && live && i >= j) col[buf][i] = a[0];
+      __syncthreads();
+      const double ljj = real_(col[buf][j]);
+      if (live && i > j) {
+        T sum = zero_<T>();
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+          const int k = grp + 8 * ((t + jb) & (KT - 1));
+          if (k > j && k <= i) sum = fma_(a[t], col[buf][k], sum);
+        }
+        red[grp][i] = sum;
+      }
+      __syncthreads();
+      if (grp == jr && live && i >= j) {
+        if (i == j) {
+          a[0] = from_real_(1.0 / ljj, zero_<T>());
+        } else {
+          T sum = red[0][i];
+#pragma unroll
+          for (int g = 1; g < 8; ++g) sum = add_(sum, red[g][i]);
+          a[0] = scale_(-1.0 / ljj, sum);
+        }
+      }
+      buf ^= 1;
+    }
+  }
+  R = 0;
+  // U[k][i] = conj(X[i][k]) for k <= i, zero below the diagonal of U
+  if (live) {
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      const int k = grp + 8 * ((t + R) & (KT - 1));
+      if (k < n) {
+        if (k <= i) U[k + (int64_t)i * n] = conj_(a[t]);
+        else U[k + (int64_t)i * n] = zero_<T>();
+      }
+    }
+  }
+  if (tid == 0) *info = 0;
+}
+
+// Split-K chunk count of a Gram product: about one block per compute unit
+// over all output tiles, chunks a multiple of GKB doubles long.
+struct GramShape {
+  int tiles_m, tiles_n, chunks;
+  int64_t kc2;
+};
+GramShape gram_shape(bool cplx, int64_t K, int m, int n) {
+  GramShape g;
+  g.tiles_m = (m + 127) / 128;
+  g.tiles_n = (n + (cplx ? 63 : 127)) / (cplx ? 64 : 128);
+  const int64_t K2 = cplx ? 2 * K : K;
+  const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
+  int64_t chunks = std::max<int64_t>(1, 256 / tiles);
+  chunks = std::min<int64_t>(chunks, (K2 + GKB - 1) / GKB);
+  g.kc2 = ((K2 + chunks - 1) / chunks + GKB - 1) / GKB * GKB;
+  g.chunks = (int)((K2 + g.kc2 - 1) / g.kc2);
+  return g;
+}
 }  // namespace
 
 // Launchers (declared in launch.h).  cplx selects complex128.
-hipError_t launch_ace_gram(bool cplx, int64_t K, int m, int n, const void* A, int64_t lda, const void* B,
-                           int64_t ldb, double alpha, void* part, int64_t kc, void* C, hipStream_t s) {
-  return cplx ? gram<Z>(K, m, n, A, lda, B, ldb, alpha, part, kc, C, s)
-              : gram<double>(K, m, n, A, lda, B, ldb, alpha, part, kc, C, s);
+int64_t ace_gram_part_bytes(bool cplx, int64_t K, int m, int n) {
+  if (K <= 0 || m <= 0 || n <= 0) return 0;
+  const GramShape g = gram_shape(cplx, K, m, n);
+  return (int64_t)g.chunks * g.tiles_m * g.tiles_n * GTILE * (int64_t)sizeof(double);
 }
 
-// LDS-resident factorization up to these orders (128 KiB of LDS)
-constexpr int kLdsNReal = 128, kLdsNCplx = 90;
-
-hipError_t launch_ace_potrf(bool cplx, int n, void* S, int* info, hipStream_t s) {
-  const int th = std::min(1024, std::max(64, (n + 63) / 64 * 64));
-  if (cplx) {
-    if (n <= kLdsNCplx) hipLaunchKernelGGL((k_potrf_lower_lds<Z, kLdsNCplx>), dim3(1), dim3(th), 0, s, n, (Z*)S, info);
-    else hipLaunchKernelGGL(k_potrf_lower<Z>, dim3(1), dim3(th), 0, s, n, (Z*)S, info);
-  } else {
-    if (n <= kLdsNReal)
-      hipLaunchKernelGGL((k_potrf_lower_lds<double, kLdsNReal>), dim3(1), dim3(th), 0, s, n, (double*)S, info);
-    else hipLaunchKernelGGL(k_potrf_lower<double>, dim3(1), dim3(th), 0, s, n, (double*)S, info);
-  }
+hipError_t launch_ace_gram(bool cplx, int64_t K, int m, int n, const void* A, int64_t lda, const void* B,
+                           int64_t ldb, double alpha, void* part, void* C, hipStream_t s) {
+  if (K <= 0 || m <= 0 || n <= 0) return hipSuccess;
+  const GramShape g = gram_shape(cplx, K, m, n);
+  const int64_t K2 = cplx ? 2 * K : K, f = cplx ? 2 : 1;
+  dim3 grid(g.chunks, g.tiles_m, g.tiles_n);
+  if (cplx)
+    hipLaunchKernelGGL(k_gram_mfma<true>, grid, dim3(256), 0, s, K2, m, n, (const double*)A, f * lda,
+                       (const double*)B, f * ldb, (double*)part, g.kc2);
+  else
+    hipLaunchKernelGGL(k_gram_mfma<false>, grid, dim3(256), 0, s, K2, m, n, (const double*)A, f * lda,
+                       (const double*)B, f * ldb, (double*)part, g.kc2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t per_chunk = (int64_t)g.tiles_m * g.tiles_n * GTILE;
+  const int blocks = (int)(per_chunk / 64);
+  if (cplx)
+    hipLaunchKernelGGL(k_gram_mfma_reduce<true>, dim3(blocks), dim3(256), 0, s, g.chunks, g.tiles_n, per_chunk, m,
+                       n, (const double*)part, alpha, (double*)C);
+  else
+    hipLaunchKernelGGL(k_gram_mfma_reduce<false>, dim3(blocks), dim3(256), 0, s, g.chunks, g.tiles_n, per_chunk,
+                       m, n, (const double*)part, alpha, (double*)C);
   return hipGetLastError();
 }
 
-hipError_t launch_ace_trtri(bool cplx, int n, const void* L, void* U, void* X, const int* info, hipStream_t s) {
+// Register-resident factorization and inverse up to this order
+constexpr int kRegN = 128;
+
+hipError_t launch_ace_factor(bool cplx, int n, void* S, void* U, void* X, int* info, hipStream_t s) {
   const int th = std::min(1024, std::max(64, (n + 63) / 64 * 64));
-  if (cplx) {
-    if (n <= kLdsNCplx)
-      hipLaunchKernelGGL((k_trtri_lower_ch_lds<Z, kLdsNCplx>), dim3(1), dim3(th), 0, s, n, (const Z*)L, (Z*)U, info);
-    else hipLaunchKernelGGL(k_trtri_lower_ch<Z>, dim3(1), dim3(th), 0, s, n, (const Z*)L, (Z*)U, (Z*)X, info);
-  } else {
-    if (n <= kLdsNReal)
-      hipLaunchKernelGGL((k_trtri_lower_ch_lds<double, kLdsNReal>), dim3(1), dim3(th), 0, s, n, (const double*)L,
-                         (double*)U, info);
+  if (n <= kRegN) {
+    if (cplx)
+      hipLaunchKernelGGL(k_chol_inv_reg<Z>, dim3(1), dim3(1024), 0, s, n, (const Z*)S, (Z*)U, info);
     else
-      hipLaunchKernelGGL(k_trtri_lower_ch<double>, dim3(1), dim3(th), 0, s, n, (const double*)L, (double*)U,
-                         (double*)X, info);
+      hipLaunchKernelGGL(k_chol_inv_reg<double>, dim3(1), dim3(1024), 0, s, n, (const double*)S, (double*)U, info);
+    return hipGetLastError();
+  }
+  // larger orders: the factor and the inverse from global memory
+  if (cplx) {
+    hipLaunchKernelGGL(k_potrf_lower<Z>, dim3(1), dim3(th), 0, s, n, (Z*)S, info);
+    hipLaunchKernelGGL(k_trtri_lower_ch<Z>, dim3(1), dim3(std::max(64, (n + 63) / 64 * 64)), 0, s, n,
+                       (const Z*)S, (Z*)U, (Z*)X, (const int*)info);
+  } else {
+    hipLaunchKernelGGL(k_potrf_lower<double>, dim3(1), dim3(th), 0, s, n, (double*)S, info);
+    hipLaunchKernelGGL(k_trtri_lower_ch<double>, dim3(1), dim3(std::max(64, (n + 63) / 64 * 64)), 0, s, n,
+                       (const double*)S, (double*)U, (double*)X, (const int*)info);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_ace_tsmm(bool cplx, int64_t K, int m, int n, const void* A, int64_t lda, const void* B,
                            double alpha, double beta, void* C, int64_t ldc, const int* info, hipStream_t s) {
-  if (K <= 0 || n <= 0) return hipSuccess;
+  if (K <= 0 || m <= 0 || n <= 0) return hipSuccess;
+  if (m <= 128) {
+    const int64_t tiles = (K + 31) / 32;
+    const int bx = (int)std::min<int64_t>((tiles + 3) / 4, device_cu_count());
+    const int nj = cplx ? 64 : 128;
+    dim3 grid(bx, (n + nj - 1) / nj);
+    if (cplx)
+      hipLaunchKernelGGL(k_tsmm_mfma<true>, grid, dim3(256), 0, s, K, m, n, (const double*)A, lda,
+                         (const double*)B, alpha, beta, (double*)C, ldc, info);
+    else
+      hipLaunchKernelGGL(k_tsmm_mfma<false>, grid, dim3(256), 0, s, K, m, n, (const double*)A, lda,
+                         (const double*)B, alpha, beta, (double*)C, ldc, info);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((K + TB - 1) / TB), (n + TB - 1) / TB);
   if (cplx)
     hipLaunchKernelGGL(k_tsmm<Z>, grid, dim3(THR), 0, s, K, m, n, (const Z*)A, lda, (const Z*)B, alpha, beta,
                        (Z*)C, ldc, info);
   else
-    hipLaunchKernelGGL(k_tsmm<double>, grid, dim3(THR), 0, s, K, m, n, (const double*)A, lda,
-                       (const double*)B, alpha, beta, (double*)C, ldc, info);
+    hipLaunchKernelGGL(k_tsmm<double>, grid, dim3(THR), 0, s, K, m, n, (const double*)A, lda, (const double*)B,
+                       alpha, beta, (double*)C, ldc, info);
   return hipGetLastError();
 }
 

@@ -83,10 +83,13 @@ hipError_t launch_slice_inv_c(bool f64, int nk, int variant, const AccArgs& a, i
 //   potrf: lower Cholesky factor of S (n x n) in place; *info = 0 or j+1
 //   trtri: U = L^{-H} (upper), X = L^{-1} scratch, both n x n; skipped if *info
 //   tsmm:  C(K x n) = beta C + alpha A(K x m) B(m x n, ld m); skipped if info && *info
+// Bytes of split-K partials launch_ace_gram needs for a K x m by K x n product.
+int64_t ace_gram_part_bytes(bool cplx, int64_t K, int m, int n);
 hipError_t launch_ace_gram(bool cplx, int64_t K, int m, int n, const void* A, int64_t lda, const void* B,
-                           int64_t ldb, double alpha, void* part, int64_t kc, void* C, hipStream_t s);
-hipError_t launch_ace_potrf(bool cplx, int n, void* S, int* info, hipStream_t s);
-hipError_t launch_ace_trtri(bool cplx, int n, const void* L, void* U, void* X, const int* info, hipStream_t s);
+                           int64_t ldb, double alpha, void* part, void* C, hipStream_t s);
+// Cholesky factor and inverse of the Hermitian n x n S: S = L L^H, U = L^{-H}; X is n x n scratch for orders above the
+// LDS-resident kernel's limit; *info = 0 or the failing pivot (1-based).
+hipError_t launch_ace_factor(bool cplx, int n, void* S, void* U, void* X, int* info, hipStream_t s);
 hipError_t launch_ace_tsmm(bool cplx, int64_t K, int m, int n, const void* A, int64_t lda, const void* B,
                            double alpha, double beta, void* C, int64_t ldc, const int* info, hipStream_t s);
 

@@ -100,17 +100,29 @@ def test_null_plan_errors():
 
 
 def test_ace_workspace_size_and_argument_errors():
-    # host-only: the workspace formula (split-K partials of 512-row chunks,
-    # 256-byte aligned, plus the small n_s x n_s matrices) and EINVAL before
-    # any device work
-    N, ns = 373248, 128
-    chunks = -(-N // 512)
-    part = chunks * ns * ns * 8
-    small = (3 * ns * ns + ns) * 8
+    # host-only: the workspace formula (split-K partials of the MFMA Gram
+    # product: about 256 blocks over the 128 x 128 (complex 128 x 64) output
+    # tiles, chunks a multiple of 64 doubles, each chunk x tile a 128 KiB
+    # partial; 256-byte aligned; plus the small n_s x n_s matrices) and EINVAL
+    # before any device work
+    def part_bytes(N, m, n, cplx):
+        tiles = -(-m // 128) * -(-n // (64 if cplx else 128))
+        K2 = N * (2 if cplx else 1)
+        chunks = min(max(1, 256 // tiles), -(-K2 // 64))
+        kc2 = -(-(-(-K2 // chunks)) // 64) * 64
+        return -(-K2 // kc2) * tiles * 128 * 128 * 8
+
     align = lambda b: (b + 255) // 256 * 256
-    assert kronx.kx_ace_workspace_bytes(N, ns, 0, False) == align(part) + align(small)
-    assert kronx.kx_ace_workspace_bytes(N, ns, 200, True) == align(chunks * ns * 200 * 16) + align(
-        (3 * ns * ns + ns * 200) * 16)
+    N, ns = 373248, 128
+    assert part_bytes(N, ns, ns, False) == 254 * 128 * 1024   # 1472-row chunks
+    assert kronx.kx_ace_workspace_bytes(N, ns, 0, False) == align(part_bytes(N, ns, ns, False)) + align(
+        (3 * ns * ns + ns) * 8)
+    for (N, ns, nphi, cplx) in [(373248, 128, 200, True), (2145, 140, 130, False), (2145, 6, 5, True),
+                                (100, 1024, 1, False)]:
+        part = max(part_bytes(N, ns, ns, cplx), part_bytes(N, ns, nphi, cplx))
+        eb = 16 if cplx else 8
+        assert kronx.kx_ace_workspace_bytes(N, ns, nphi, cplx) == align(part) + align(
+            (3 * ns * ns + ns * nphi) * eb), (N, ns, nphi, cplx)
     lib = kronx.load_library()
     for bad in [(0, 4), (100, 0), (100, 1025)]:
         out = ctypes.c_int64(0)

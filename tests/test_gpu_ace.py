@@ -69,6 +69,45 @@ def test_ace_matches_oracle(kx, kind, nb):
     assert rel_fro(to_host(vphi), ref) < 1e-12
 
 
+@pytest.mark.parametrize("kind", ["real", "complex"])
+@pytest.mark.parametrize("ns", [6, 70, 100, 140])
+def test_ace_ragged_grid_and_large_orbital_sets(kx, kind, ns):
+    # N = 15*13*11 = 2145: ragged against the 32-row tiles and split-K chunks;
+    # n_s = 100 and 140 take the global-memory factorization for complex
+    # (above 90) and, at 140, for real too, plus the VALU tall-skinny product
+    # (n_s above 128); n_phi = 130 spans several output tiles.
+    # W = -Psi (B B^H + I) gives M = -(B B^H + I), Hermitian negative definite
+    n, h = (15, 13, 11), (0.4, 0.4, 0.4)
+    say("ace ragged", kind, ns)
+    if kind == "real":
+        psi = random_orbitals(n, h, ns, seed=70 + ns)
+    else:
+        L = [n[d] * h[d] for d in range(3)]
+        psi = random_orbitals(n, h, ns, seed=70 + ns, kpt=(2 * np.pi / L[0] * 0.25, 0.0, 0.0), decay=2.0)
+    dV = float(np.prod(h))
+    rng = np.random.default_rng(70 + ns)
+    B = rng.standard_normal((ns, ns)) / np.sqrt(ns)
+    if kind == "complex":
+        B = B + 1j * rng.standard_normal((ns, ns)) / np.sqrt(ns)
+    W = np.ascontiguousarray(-(psi.T @ (B @ B.conj().T + np.eye(ns))).T)
+    xi_ref = ace_construct(psi, W, dV)
+    ct = torch.float64 if kind == "real" else torch.complex128
+    xi = kx.ace_construct(to_dev(psi, ct), to_dev(W, ct), dV)
+    torch.cuda.synchronize()
+    assert rel_fro(to_host(xi), xi_ref) < 1e-11
+    for n_phi in (5, 130):
+        phi = rng.standard_normal((n_phi, psi.shape[1]))
+        v0 = rng.standard_normal(phi.shape)
+        if kind == "complex":
+            phi = phi + 1j * rng.standard_normal(phi.shape)
+            v0 = v0 + 1j * rng.standard_normal(phi.shape)
+        vphi = to_dev(v0, ct)
+        kx.ace_apply(xi, to_dev(phi, ct), dV, vphi)
+        torch.cuda.synchronize()
+        ref = v0 + ace_apply(xi_ref, phi, dV)
+        assert rel_fro(to_host(vphi), ref) < 1e-11, n_phi
+
+
 def test_device_chain_reproduces_w(kx):
     # W = Vx Psi from exx_apply, then ACE from it: the compressed operator
     # returns W on the orbitals
