@@ -63,132 +63,6 @@ __device__ __forceinline__ double real_(Z a) { return a.re; }
 __device__ __forceinline__ double abs2_(double a) { return a * a; }
 __device__ __forceinline__ double abs2_(Z a) { return a.re * a.re + a.im * a.im; }
 
-constexpr int TB = 64;   // output tile edge
-constexpr int KB = 32;   // K rows staged per step
-constexpr int THR = 256; // 16 x 16 threads, 4 x 4 outputs each
-
-// In-place lower Cholesky factor of the Hermitian positive definite n x n
-// matrix S (column-major, ld n): S = L L^H, L overwrites the lower triangle.
-// One workgroup; *info = 0, or j+1 if the j-th pivot is not positive (then
-// the factor is incomplete).  Left-looking: column j needs columns < j.
-template <typename T>
-__global__ void __launch_bounds__(1024) k_potrf_lower(int n, T* S, int* info) {
-  __shared__ double red[32];
-  __shared__ int bad;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  if (tid == 0) bad = 0;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    // pivot: d = S[j][j] - sum_k |L[j][k]|^2, fixed-order reduction
-    double part = 0.0;
-    for (int k = tid; k < j; k += nthr) part += abs2_(S[j + (int64_t)k * n]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = part;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      for (int w = 0; w < (nthr + 63) / 64; ++w) s += red[w];
-      const double d = real_(S[j + (int64_t)j * n]) - s;
-      if (!(d > 0.0)) {
-        bad = j + 1;
-      } else {
-        S[j + (int64_t)j * n] = from_real_(sqrt(d), zero_<T>());
-      }
-    }
-    __syncthreads();
-    if (bad) break;
-    const double inv = 1.0 / real_(S[j + (int64_t)j * n]);
-    for (int i = j + 1 + tid; i < n; i += nthr) {
-      T s = S[i + (int64_t)j * n];
-      for (int k = 0; k < j; ++k) s = sub_(s, mul_(S[i + (int64_t)k * n], conj_(S[j + (int64_t)k * n])));
-      S[i + (int64_t)j * n] = scale_(inv, s);
-    }
-    __syncthreads();
-  }
-  if (tid == 0) *info = bad;
-}
-
-// U = L^{-H} (upper triangular, column-major, ld n) from the lower factor L
-// (ld n).  Thread j solves L x = e_j for column j of X = L^{-1} and writes
-// row j of U = X^H.  Skipped when *info != 0.
-template <typename T>
-__global__ void __launch_bounds__(1024) k_trtri_lower_ch(int n, const T* L, T* U, T* X, const int* info) {
-  if (*info) return;
-  const int j = threadIdx.x;
-  if (j >= n) return;
-  for (int i = 0; i < j; ++i) {
-    X[i + (int64_t)j * n] = zero_<T>();
-    U[j + (int64_t)i * n] = zero_<T>();
-  }
-  for (int i = j; i < n; ++i) {
-    T s = (i == j) ? one_<T>() : zero_<T>();
-    for (int k = j; k < i; ++k) s = sub_(s, mul_(L[i + (int64_t)k * n], X[k + (int64_t)j * n]));
-    const T x = scale_(1.0 / real_(L[i + (int64_t)i * n]), s);
-    X[i + (int64_t)j * n] = x;
-    U[j + (int64_t)i * n] = conj_(x);
-  }
-}
-
-// C(K x n) = beta * C + alpha * A(K x m) B(m x n); B small (ld m).
-// grid = (row tiles of 64, column tiles of 64); skipped when info && *info.
-template <typename T>
-__global__ void __launch_bounds__(THR) k_tsmm(int64_t K, int m, int n, const T* __restrict__ A, int64_t lda,
-                                              const T* __restrict__ B, double alpha, double beta, T* C,
-                                              int64_t ldc, const int* info) {
-  if (info && *info) return;
-  __shared__ T As[KB][TB + 1], Bs[KB][TB + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int64_t k0 = (int64_t)blockIdx.x * TB;
-  const int j0 = blockIdx.y * TB;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = zero_<T>();
-  for (int i0 = 0; i0 < m; i0 += KB) {
-    // As[ii][r] = A[k0 + r, i0 + ii] (rows contiguous); Bs[ii][c] = B[i0 + ii, j0 + c]
-#pragma unroll
-    for (int r = 0; r < TB * KB / THR; ++r) {
-      const int e = tid + r * THR;
-      {
-        const int rr = e % TB, ii = e / TB;
-        const int64_t k = k0 + rr;
-        As[ii][rr] = (k < K && i0 + ii < m) ? A[k + (int64_t)(i0 + ii) * lda] : zero_<T>();
-      }
-      {
-        const int ii = e % KB, c = e / KB;
-        Bs[ii][c] = (i0 + ii < m && j0 + c < n) ? B[(i0 + ii) + (int64_t)(j0 + c) * m] : zero_<T>();
-      }
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int ii = 0; ii < KB; ++ii) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[ii][tx + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[ii][ty + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma_(av[a], bv[b], acc[a][b]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t k = k0 + tx + 16 * a;
-      const int j = j0 + ty + 16 * b;
-      if (k < K && j < n) {
-        T* c = C + k + (int64_t)j * ldc;
-        *c = (beta == 0.0) ? scale_(alpha, acc[a][b]) : add_(scale_(beta, *c), scale_(alpha, acc[a][b]));
-      }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // MFMA forms (v_mfma_f64_16x16x4).  Operand layout, lane l = 16*lg + lr:
 // A fragment A[row = lr][k = lg], B fragment B[k = lg][col = lr], accumulator
@@ -349,8 +223,9 @@ __global__ void __launch_bounds__(256) k_gram_mfma_reduce(int chunks, int tiles_
 constexpr int TQ = 258;  // LDS pitch (doubles) of the B tile: 2 mod 32
 template <bool CPLX>
 __global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, const double* __restrict__ A,
-                                                   int64_t lda, const double* __restrict__ B, double alpha,
-                                                   double beta, double* C, int64_t ldc, const int* info) {
+                                                   int64_t lda, const double* __restrict__ B, int ldb,
+                                                   double alpha, double beta, double* C, int64_t ldc,
+                                                   const int* info) {
   if (info && *info) return;
   constexpr int NJ = CPLX ? 64 : 128, NTJ = 4, SETS = CPLX ? 2 : 1, G = 8;
   constexpr int PITCH = CPLX ? TQ : 130;
@@ -363,7 +238,7 @@ __global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, cons
   // X[j][q] = B as doubles: column j of B is contiguous in q
   for (int e = tid; e < NJ * PITCH; e += 256) {
     const int j = e / PITCH, q = e % PITCH;
-    Xs[e] = (q < Q && j0 + j < n) ? B[q + (int64_t)(j0 + j) * Q] : 0.0;
+    Xs[e] = (q < Q && j0 + j < n) ? B[q + (int64_t)(j0 + j) * (CPLX ? 2 * ldb : ldb)] : 0.0;
   }
   __syncthreads();
   const int tiles = (int)((K + 31) / 32);
@@ -496,11 +371,14 @@ __global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, cons
 // block, already in place):
 //   x_jj = 1/l_jj,  x_(j+1:, j) = -X_22 l_(j+1:, j) / l_jj,
 // the products split over the 8 groups and summed in group order.
-// Writes U = L^{-H} = X^H (upper, ld n) and *info: 0, or j+1 at the first
-// non-positive pivot (U then left untouched).
+// Writes U = L^{-H} = X^H (upper, zeros below, ld ldu) and *info: j+1+base at
+// the first non-positive pivot (U then left untouched); on success *info is
+// set to 0 when base == 0 and left alone otherwise.  With base > 0 (a
+// diagonal tile of a larger matrix) the kernel does nothing if *info != 0.
 template <typename T>
-__global__ void __launch_bounds__(1024) k_chol_inv_reg(int n, const T* __restrict__ S, T* __restrict__ U,
-                                                       int* info) {
+__global__ void __launch_bounds__(1024) k_chol_inv_reg(int n, const T* __restrict__ S, int lds, T* __restrict__ U,
+                                                       int ldu, int* info, int base) {
+  if (base > 0 && *info) return;
   constexpr int KT = 16;
   __shared__ T col[2][128];
   __shared__ T red[8][128];
@@ -511,7 +389,7 @@ __global__ void __launch_bounds__(1024) k_chol_inv_reg(int n, const T* __restric
   for (int t = 0; t < KT; ++t) {
     const int k = grp + 8 * t;
     a[t] = zero_<T>();
-    if (live && k < n) a[t] = S[i + (int64_t)k * n];
+    if (live && k < n) a[t] = S[i + (int64_t)k * lds];
   }
   // Slot t holds column block (t + R) mod 16 (column j = 8 * block + grp).
   // The block being eliminated is kept in slot 0 by rotating the slots once
@@ -555,7 +433,7 @@ __global__ void __launch_bounds__(1024) k_chol_inv_reg(int n, const T* __restric
     rot_left();
   }
   if (bad) {
-    if (tid == 0) *info = bad;
+    if (tid == 0) *info = bad + base;
     return;
   }
   int R = nblk & (KT - 1);
@@ -613,12 +491,83 @@ __global__ void __launch_bounds__(1024) k_chol_inv_reg(int n, const T* __restric
     for (int t = 0; t < KT; ++t) {
       const int k = grp + 8 * ((t + R) & (KT - 1));
       if (k < n) {
-        if (k <= i) U[k + (int64_t)i * n] = conj_(a[t]);
-        else U[k + (int64_t)i * n] = zero_<T>();
+        if (k <= i) U[k + (int64_t)i * ldu] = conj_(a[t]);
+        else U[k + (int64_t)i * ldu] = zero_<T>();
       }
     }
   }
-  if (tid == 0) *info = 0;
+  if (tid == 0 && base == 0) *info = 0;
+}
+
+// Small dense products for the tiled factorization (orders above 128):
+// C(m x n) = beta C + alpha A(m x k) op(B), op(B) = B (k x n) or, with BH,
+// B^H for B stored n x k; all column-major.  64 x 64 tile per block of 256
+// threads (4 x 4 outputs each), 16-deep K steps through LDS.  Skipped when
+// *info != 0.
+template <typename T, bool BH>
+__global__ void __launch_bounds__(256) k_small_gemm(int m, int n, int k, double alpha, const T* __restrict__ A,
+                                                    int lda, const T* __restrict__ B, int ldb, double beta,
+                                                    T* __restrict__ C, int ldc, const int* info) {
+  if (*info) return;
+  __shared__ T As[16][65], Bs[16][65];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = zero_<T>();
+  for (int p0 = 0; p0 < k; p0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int r = e % 64, p = e / 64;  // A[i0 + r][p0 + p]
+      As[p][r] = (i0 + r < m && p0 + p < k) ? A[(i0 + r) + (int64_t)(p0 + p) * lda] : zero_<T>();
+      if (BH) {  // op(B)[p][c] = conj(B[c][p])
+        const int c = e % 64, pp = e / 64;
+        Bs[pp][c] = (j0 + c < n && p0 + pp < k) ? conj_(B[(j0 + c) + (int64_t)(p0 + pp) * ldb]) : zero_<T>();
+      } else {
+        const int pp = e % 16, c = e / 16;
+        Bs[pp][c] = (j0 + c < n && p0 + pp < k) ? B[(p0 + pp) + (int64_t)(j0 + c) * ldb] : zero_<T>();
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int p = 0; p < 16; ++p) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[p][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[p][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma_(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+      if (i < m && j < n) {
+        T* c = C + i + (int64_t)j * ldc;
+        const T v = scale_(alpha, acc[a][b]);
+        *c = (beta == 0.0) ? v : add_(scale_(beta, *c), v);
+      }
+    }
+}
+
+// dst(m x n) = src^H for src n x m; with LOWER only the lower triangle of src
+// is read (dst gets zeros below its diagonal).  Skipped when *info != 0.
+template <typename T, bool LOWER>
+__global__ void k_conj_transpose(int m, int n, const T* __restrict__ src, int lds, T* __restrict__ dst, int ldd,
+                                 const int* info) {
+  if (*info) return;
+  const int64_t total = (int64_t)m * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);  // dst[i][j] = conj(src[j][i])
+    dst[i + (int64_t)j * ldd] = (!LOWER || j >= i) ? conj_(src[j + (int64_t)i * lds]) : zero_<T>();
+  }
 }
 
 // Split-K chunk count of a Gram product: about one block per compute unit
@@ -673,55 +622,105 @@ hipError_t launch_ace_gram(bool cplx, int64_t K, int m, int n, const void* A, in
   return hipGetLastError();
 }
 
-// Register-resident factorization and inverse up to this order
+// Register-resident factorization and inverse of one tile of up to this order
 constexpr int kRegN = 128;
 
+namespace {
+template <typename T>
+hipError_t small_gemm(bool bh, int m, int n, int k, double alpha, const T* A, int lda, const T* B, int ldb,
+                      double beta, T* C, int ldc, const int* info, hipStream_t s) {
+  dim3 grid((m + 63) / 64, (n + 63) / 64);
+  if (bh) hipLaunchKernelGGL((k_small_gemm<T, true>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, info);
+  else hipLaunchKernelGGL((k_small_gemm<T, false>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, info);
+  return hipGetLastError();
+}
+
+// Tiled Cholesky factor and inverse of the n x n Hermitian S (tiles of 128):
+//   for each diagonal tile kb: U_kk = L_kk^{-H} (register kernel, into X);
+//   panel L_ik = S_ik U_kk (into X); trailing S_ij -= L_ik L_jk^H.
+//   Y = L^{-1} (into S): Y_jj = U_jj^H; Y_ij = -Y_ii (sum_{k=j}^{i-1} L_ik Y_kj)
+//   with the sums in U as scratch; finally U = Y^H.
+template <typename T>
+hipError_t factor_tiled(int n, T* S, T* U, T* X, int* info, hipStream_t s) {
+  const int nt = (n + kRegN - 1) / kRegN;
+  auto off = [&](int ib, int jb) { return (int64_t)ib * kRegN + (int64_t)jb * kRegN * n; };
+  auto sz = [&](int ib) { return std::min(kRegN, n - ib * kRegN); };
+  hipError_t e = hipSuccess;
+  for (int kb = 0; kb < nt && e == hipSuccess; ++kb) {
+    hipLaunchKernelGGL(k_chol_inv_reg<T>, dim3(1), dim3(1024), 0, s, sz(kb), (const T*)(S + off(kb, kb)), n,
+                       X + off(kb, kb), n, info, kb * kRegN);
+    e = hipGetLastError();
+    for (int ib = kb + 1; ib < nt && e == hipSuccess; ++ib)
+      e = small_gemm<T>(false, sz(ib), sz(kb), sz(kb), 1.0, S + off(ib, kb), n, X + off(kb, kb), n, 0.0,
+                        X + off(ib, kb), n, info, s);
+    for (int jb = kb + 1; jb < nt && e == hipSuccess; ++jb)
+      for (int ib = jb; ib < nt && e == hipSuccess; ++ib)
+        e = small_gemm<T>(true, sz(ib), sz(jb), sz(kb), -1.0, X + off(ib, kb), n, X + off(jb, kb), n, 1.0,
+                          S + off(ib, jb), n, info, s);
+  }
+  for (int jb = 0; jb < nt && e == hipSuccess; ++jb) {
+    const int64_t tot = (int64_t)sz(jb) * sz(jb);
+    hipLaunchKernelGGL((k_conj_transpose<T, false>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, sz(jb),
+                       sz(jb), (const T*)(X + off(jb, jb)), n, S + off(jb, jb), n, (const int*)info);
+    e = hipGetLastError();
+  }
+  for (int jb = 0; jb < nt && e == hipSuccess; ++jb)
+    for (int ib = jb + 1; ib < nt && e == hipSuccess; ++ib) {
+      for (int kb = jb; kb < ib && e == hipSuccess; ++kb)
+        e = small_gemm<T>(false, sz(ib), sz(jb), sz(kb), 1.0, X + off(ib, kb), n, S + off(kb, jb), n,
+                          kb == jb ? 0.0 : 1.0, U + off(ib, jb), n, info, s);
+      if (e == hipSuccess)
+        e = small_gemm<T>(false, sz(ib), sz(jb), sz(ib), -1.0, S + off(ib, ib), n, U + off(ib, jb), n, 0.0,
+                          S + off(ib, jb), n, info, s);
+    }
+  if (e == hipSuccess) {
+    const int64_t tot = (int64_t)n * n;
+    hipLaunchKernelGGL((k_conj_transpose<T, true>), dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 4096)),
+                       dim3(256), 0, s, n, n, (const T*)S, n, U, n, (const int*)info);
+    e = hipGetLastError();
+  }
+  return e;
+}
+}  // namespace
+
 hipError_t launch_ace_factor(bool cplx, int n, void* S, void* U, void* X, int* info, hipStream_t s) {
-  const int th = std::min(1024, std::max(64, (n + 63) / 64 * 64));
   if (n <= kRegN) {
     if (cplx)
-      hipLaunchKernelGGL(k_chol_inv_reg<Z>, dim3(1), dim3(1024), 0, s, n, (const Z*)S, (Z*)U, info);
+      hipLaunchKernelGGL(k_chol_inv_reg<Z>, dim3(1), dim3(1024), 0, s, n, (const Z*)S, n, (Z*)U, n, info, 0);
     else
-      hipLaunchKernelGGL(k_chol_inv_reg<double>, dim3(1), dim3(1024), 0, s, n, (const double*)S, (double*)U, info);
+      hipLaunchKernelGGL(k_chol_inv_reg<double>, dim3(1), dim3(1024), 0, s, n, (const double*)S, n, (double*)U, n,
+                         info, 0);
     return hipGetLastError();
   }
-  // larger orders: the factor and the inverse from global memory
-  if (cplx) {
-    hipLaunchKernelGGL(k_potrf_lower<Z>, dim3(1), dim3(th), 0, s, n, (Z*)S, info);
-    hipLaunchKernelGGL(k_trtri_lower_ch<Z>, dim3(1), dim3(std::max(64, (n + 63) / 64 * 64)), 0, s, n,
-                       (const Z*)S, (Z*)U, (Z*)X, (const int*)info);
-  } else {
-    hipLaunchKernelGGL(k_potrf_lower<double>, dim3(1), dim3(th), 0, s, n, (double*)S, info);
-    hipLaunchKernelGGL(k_trtri_lower_ch<double>, dim3(1), dim3(std::max(64, (n + 63) / 64 * 64)), 0, s, n,
-                       (const double*)S, (double*)U, (double*)X, (const int*)info);
-  }
-  return hipGetLastError();
+  return cplx ? factor_tiled<Z>(n, (Z*)S, (Z*)U, (Z*)X, info, s)
+              : factor_tiled<double>(n, (double*)S, (double*)U, (double*)X, info, s);
 }
 
 hipError_t launch_ace_tsmm(bool cplx, int64_t K, int m, int n, const void* A, int64_t lda, const void* B,
                            double alpha, double beta, void* C, int64_t ldc, const int* info, hipStream_t s) {
   if (K <= 0 || m <= 0 || n <= 0) return hipSuccess;
-  if (m <= 128) {
-    const int64_t tiles = (K + 31) / 32;
-    const int bx = (int)std::min<int64_t>((tiles + 3) / 4, device_cu_count());
-    const int nj = cplx ? 64 : 128;
-    dim3 grid(bx, (n + nj - 1) / nj);
+  // contraction slabs of at most 128 (B's column tile must fit in LDS);
+  // slabs after the first accumulate
+  const int64_t tiles = (K + 31) / 32;
+  const int bx = (int)std::min<int64_t>((tiles + 3) / 4, device_cu_count());
+  const int nj = cplx ? 64 : 128;
+  const int64_t f = cplx ? 2 : 1;  // doubles per element
+  dim3 grid(bx, (n + nj - 1) / nj);
+  for (int q0 = 0; q0 < m; q0 += 128) {
+    const int mq = std::min(128, m - q0);
+    const double* As = (const double*)A + f * (int64_t)q0 * lda;
+    const double* Bs = (const double*)B + f * q0;
+    const double bq = q0 == 0 ? beta : 1.0;
     if (cplx)
-      hipLaunchKernelGGL(k_tsmm_mfma<true>, grid, dim3(256), 0, s, K, m, n, (const double*)A, lda,
-                         (const double*)B, alpha, beta, (double*)C, ldc, info);
+      hipLaunchKernelGGL(k_tsmm_mfma<true>, grid, dim3(256), 0, s, K, mq, n, As, lda, Bs, m, alpha, bq, (double*)C,
+                         ldc, info);
     else
-      hipLaunchKernelGGL(k_tsmm_mfma<false>, grid, dim3(256), 0, s, K, m, n, (const double*)A, lda,
-                         (const double*)B, alpha, beta, (double*)C, ldc, info);
-    return hipGetLastError();
+      hipLaunchKernelGGL(k_tsmm_mfma<false>, grid, dim3(256), 0, s, K, mq, n, As, lda, Bs, m, alpha, bq,
+                         (double*)C, ldc, info);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  dim3 grid((unsigned)((K + TB - 1) / TB), (n + TB - 1) / TB);
-  if (cplx)
-    hipLaunchKernelGGL(k_tsmm<Z>, grid, dim3(THR), 0, s, K, m, n, (const Z*)A, lda, (const Z*)B, alpha, beta,
-                       (Z*)C, ldc, info);
-  else
-    hipLaunchKernelGGL(k_tsmm<double>, grid, dim3(THR), 0, s, K, m, n, (const double*)A, lda, (const double*)B,
-                       alpha, beta, (double*)C, ldc, info);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace kx

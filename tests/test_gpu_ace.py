@@ -70,12 +70,13 @@ def test_ace_matches_oracle(kx, kind, nb):
 
 
 @pytest.mark.parametrize("kind", ["real", "complex"])
-@pytest.mark.parametrize("ns", [6, 70, 100, 140])
+@pytest.mark.parametrize("ns", [6, 70, 128, 140, 260])
 def test_ace_ragged_grid_and_large_orbital_sets(kx, kind, ns):
     # N = 15*13*11 = 2145: ragged against the 32-row tiles and split-K chunks;
-    # n_s = 100 and 140 take the global-memory factorization for complex
-    # (above 90) and, at 140, for real too, plus the VALU tall-skinny product
-    # (n_s above 128); n_phi = 130 spans several output tiles.
+    # n_s = 128 fills one factorization tile exactly, 140 and 260 take the
+    # tiled factorization (2 and 3 tiles, ragged last tile) and the
+    # tall-skinny product in contraction slabs of 128; n_phi = 130 spans
+    # several output tiles.
     # W = -Psi (B B^H + I) gives M = -(B B^H + I), Hermitian negative definite
     n, h = (15, 13, 11), (0.4, 0.4, 0.4)
     say("ace ragged", kind, ns)
@@ -147,6 +148,24 @@ def test_full_size_synthetic(kx):
     torch.cuda.synchronize()
     assert rel_fro(to_host(xi), xi_ref) < 1e-12
     assert rel_fro(to_host(v), W) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_non_definite_pivot_in_a_later_tile(kx, kind):
+    # W = -Psi D with D = diag(1, ..., 1, -1 at 200): -M = D, so the factorization
+    # of the third 128-tile stops at pivot 201 and nothing after it runs
+    n, h, ns = (15, 13, 11), (0.4, 0.4, 0.4), 260
+    if kind == "real":
+        psi = random_orbitals(n, h, ns, seed=90)
+    else:
+        L = [n[d] * h[d] for d in range(3)]
+        psi = random_orbitals(n, h, ns, seed=90, kpt=(2 * np.pi / L[0] * 0.25, 0.0, 0.0), decay=2.0)
+    d = np.ones(ns)
+    d[200] = -1.0
+    W = np.ascontiguousarray(-(psi.T * d).T)
+    ct = torch.float64 if kind == "real" else torch.complex128
+    with pytest.raises(kx.KronxError, match="pivot 201"):
+        kx.ace_construct(to_dev(psi, ct), to_dev(W, ct), float(np.prod(h)))
 
 
 def test_non_definite_reported(kx):
