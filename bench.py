@@ -320,6 +320,66 @@ def run_sweep(kx, torch, np, args):
             plan.destroy()
 
 
+def run_compare(kx, torch, np, args):
+    """Fig. compare analogue (Sec. III): time per Poisson solve (Coulomb,
+    periodic, h = 0.3) against the grid size for the original slice-wise
+    formalism of Sec. II.A (one small GEMM per frontal slice, 4 n3 + 2 GEMM
+    launches per solve) and the batched formalism of Sec. II.B (n_c = 20, the
+    paper's batch size, fused and plain), on the GPU; and the oracle's two
+    forms (slice-wise and the literal batch with its reorganizations) on the
+    host cores as the CPU baseline.  One JSON line per grid."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.kron import KronSolver
+    rng = np.random.default_rng(11)
+    cores = len(os.sched_getaffinity(0))
+    nc = 20
+
+    def gpu_ms(plan, B, X, path, reps):
+        kx.kron_solve(plan, B, X, path=path)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for i in range(reps):
+            kx.kron_solve(plan, B, X, path=path)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        t = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
+        return t[len(t) // 2]
+
+    for n in (50, 75, 100):
+        log("compare", n)
+        N = n ** 3
+        Bh = rng.standard_normal((nc, N))
+        plan = kx.kron_setup((n,) * 3, (0.3,) * 3, ("periodic",) * 3, 12, 0.0, prec="fp64")
+        try:
+            B = torch.from_numpy(Bh).cuda()
+            X = torch.empty_like(B)
+            Xs = torch.empty_like(B[:2])
+            row = dict(compare="kron_solve", grid=[n] * 3, h=0.3, kernel="coulomb", n_c=nc)
+            row["gpu_slicewise_ms_per_solve"] = round(gpu_ms(plan, B[:2], Xs, "slicewise", 5) / 2, 4)
+            row["gpu_batch_fused_ms_per_solve"] = round(gpu_ms(plan, B, X, "fused", 20) / nc, 5)
+            ref = X[:2].clone()
+            row["gpu_batch_plain_ms_per_solve"] = round(gpu_ms(plan, B, X, "plain", 20) / nc, 5)
+            row["slicewise_vs_batch_rel_diff"] = float((Xs - ref).norm() / ref.norm())
+        finally:
+            plan.destroy()
+        S = KronSolver((n,) * 3, (0.3,) * 3, ("periodic",) * 3, 12, 0.0)
+        with threadpool_limits(cores):
+            t0 = time.perf_counter()
+            S.solve(Bh[:2])
+            row["cpu_slicewise_ms_per_solve"] = round(1e3 * (time.perf_counter() - t0) / 2, 3)
+            t0 = time.perf_counter()
+            S.solve_batch(Bh)
+            row["cpu_batch_ms_per_solve"] = round(1e3 * (time.perf_counter() - t0) / nc, 3)
+        row["cpu"] = dict(kind="oracle", cores=cores, note="FP64 NumPy, one call each: slice-wise on 2 "
+                          f"right-hand sides, the literal batch on n_c = {nc}")
+        row["gpu_batch_vs_cpu_batch"] = round(row["cpu_batch_ms_per_solve"] / row["gpu_batch_fused_ms_per_solve"], 1)
+        row["gpu_batch_vs_gpu_slicewise"] = round(row["gpu_slicewise_ms_per_solve"]
+                                                  / row["gpu_batch_fused_ms_per_solve"], 1)
+        print(json.dumps(row), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +396,9 @@ def main():
     ap.add_argument("--no-ace", action="store_true", help="skip the ACE construction/application timing")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line: time per solve vs right-hand sides per call")
+    ap.add_argument("--compare", action="store_true",
+                    help="instead of the benchmark line: slice-wise (Sec. II.A) vs batched (Sec. II.B) "
+                         "time per solve on 50^3, 75^3, 100^3, GPU and host oracle")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB on the device first: a kernel of known traffic for scaling "
                          "FETCH_SIZE / WRITE_SIZE counters")
@@ -355,6 +418,9 @@ def main():
     kx.load_library()
     if args.sweep:
         run_sweep(kx, torch, np, args)
+        return
+    if args.compare:
+        run_compare(kx, torch, np, args)
         return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB

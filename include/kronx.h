@@ -87,8 +87,12 @@ enum { KX_FLAG_COMPLEX = 16 };
  *           psi_m product and the accumulation into Vx, with E_x partials.
  *   PLAIN : one kernel per step (pair density, three forward mode products,
  *           scaling, three inverse mode products, accumulation), each a full
- *           pass over the batch in device memory.  FP64 only. */
-enum { KX_PATH_FUSED = 0, KX_PATH_PLAIN = 1 };
+ *           pass over the batch in device memory.  FP64 only.
+ *   SLICEWISE (kron_solve only): the original formalism of Sec. II.A, one
+ *           right-hand side at a time and one small GEMM per frontal slice
+ *           for modes 1 and 2 (4 n3 + 2 GEMM launches per solve); the
+ *           comparison point for the batched solve.  FP64, real plans only. */
+enum { KX_PATH_FUSED = 0, KX_PATH_PLAIN = 1, KX_PATH_SLICEWISE = 2 };
 
 /* kron_setup -- build a plan for X = f(L) B on one grid (Sec. II.A,
  * Eqs. (fL), (FinalRepfL)).
@@ -118,7 +122,8 @@ kx_status kron_destroy(kx_plan p);
  *   d_B  nrhs columns, leading dimension ldb >= N, plan element type.
  *   d_X  nrhs columns, leading dimension ldx >= N, plan element type;
  *        overwritten.  d_X may not overlap d_B.
- *   path KX_PATH_*. */
+ *   path KX_PATH_*; KX_PATH_SLICEWISE uses N doubles of plan-owned
+ *        workspace (allocated on first use, KX_ENOMEM if that fails). */
 kx_status kron_solve(kx_plan p, const void* d_B, int64_t ldb, void* d_X, int64_t ldx,
                      int nrhs, int path, void* stream);
 

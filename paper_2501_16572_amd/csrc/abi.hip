@@ -783,19 +783,66 @@ kx_status kx_plan_tables(kx_plan p, int axis, double* lam, double* V_re, double*
   return KX_OK;
 }
 
+namespace {
+// Sec. II.A, one right-hand side at a time: per frontal slice k,
+//   X_k = V1^T B_k V2 (two GEMMs), then X = X V3 over the whole grid, the
+// eigen-scaling, X = X V3^T, and per slice X_k = V1 X_k V2^T (two GEMMs):
+// 4 n3 + 2 GEMM launches per solve.  The plan's eigenvector copies are padded
+// (leading dimension P12 for V1, V2 and P3 for V3); W is N doubles of plan
+// workspace (a slice of it holds each slice's intermediate product).
+kx_status kron_solve_slicewise(kx_plan p, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs,
+                               hipStream_t s) {
+  void* ws0 = p->d_ws;
+  kx_status st = ensure_buffer(&p->d_ws, &p->ws_bytes, (size_t)p->N * sizeof(double), "slice-wise workspace");
+  if (st != KX_OK) return st;
+  if (p->d_ws != ws0) ++p->ws_gen;  // cached exx graphs must re-capture
+  const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2], n12 = p->n12;
+  // dVmat[d] holds V_d[grid k][mode a] at k*P + a, i.e. V_d^T as a
+  // column-major matrix; dVmatT[d] is V_d itself, column-major
+  const double* V1 = (const double*)p->dVmatT[0];
+  const double* V1T = (const double*)p->dVmat[0];
+  const double* V2 = (const double*)p->dVmatT[1];
+  const double* V2T = (const double*)p->dVmat[1];
+  const double* V3 = (const double*)p->dVmatT[2];
+  const double* V3T = (const double*)p->dVmat[2];
+  double* W = (double*)p->d_ws;
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < nrhs && e == hipSuccess; ++r) {
+    const double* b = B + (int64_t)r * ldb;
+    double* x = X + (int64_t)r * ldx;
+    for (int k = 0; k < n3 && e == hipSuccess; ++k) {
+      e = kx::launch_gemm_nn_f64(n1, n2, n1, V1T, p->P12, b + (int64_t)k * n12, n1, W + (int64_t)k * n12, n1, s);
+      if (e == hipSuccess)
+        e = kx::launch_gemm_nn_f64(n1, n2, n2, W + (int64_t)k * n12, n1, V2, p->P12, x + (int64_t)k * n12, n1, s);
+    }
+    if (e == hipSuccess) e = kx::launch_gemm_nn_f64(n12, n3, n3, x, n12, V3, p->P3, W, n12, s);
+    if (e == hipSuccess) e = kx::launch_scale_f64(W, p->N, 1, p->N, p->d_f, s);
+    if (e == hipSuccess) e = kx::launch_gemm_nn_f64(n12, n3, n3, W, n12, V3T, p->P3, x, n12, s);
+    for (int k = 0; k < n3 && e == hipSuccess; ++k) {
+      e = kx::launch_gemm_nn_f64(n1, n2, n1, V1, p->P12, x + (int64_t)k * n12, n1, W + (int64_t)k * n12, n1, s);
+      if (e == hipSuccess)
+        e = kx::launch_gemm_nn_f64(n1, n2, n2, W + (int64_t)k * n12, n1, V2T, p->P12, x + (int64_t)k * n12, n1, s);
+    }
+  }
+  if (e != hipSuccess) return dev_fail(e, "kron_solve slice-wise launch");
+  return KX_OK;
+}
+}  // namespace
+
 kx_status kron_solve(kx_plan p, const void* B, int64_t ldb, void* X, int64_t ldx, int nrhs, int path,
                      void* stream) {
   using namespace kx;
   if (!p) return fail(KX_EINVAL, "kron_solve: plan is NULL");
   if (nrhs < 0) return fail(KX_EINVAL, "kron_solve: nrhs < 0");
-  if (path != KX_PATH_FUSED && path != KX_PATH_PLAIN) return fail(KX_EINVAL, "kron_solve: unknown path");
-  if (path == KX_PATH_PLAIN && p->prec != KX_PREC_FP64)
-    return fail(KX_EUNSUPPORTED, "kron_solve: the plain path is FP64 only");
+  if (path != KX_PATH_FUSED && path != KX_PATH_PLAIN && path != KX_PATH_SLICEWISE)
+    return fail(KX_EINVAL, "kron_solve: unknown path");
+  if (path != KX_PATH_FUSED && p->prec != KX_PREC_FP64)
+    return fail(KX_EUNSUPPORTED, "kron_solve: the plain and slice-wise paths are FP64 only");
   if (nrhs == 0) return KX_OK;
   if (!B || !X) return fail(KX_EINVAL, "kron_solve: NULL data pointer");
   if (ldb < p->N || ldx < p->N) return fail(KX_EINVAL, "kron_solve: leading dimension below N");
-  if (p->cplx && path == KX_PATH_PLAIN)
-    return fail(KX_EUNSUPPORTED, "kron_solve: the plain path is real (Gamma) only");
+  if (p->cplx && path != KX_PATH_FUSED)
+    return fail(KX_EUNSUPPORTED, "kron_solve: the plain and slice-wise paths are real (Gamma) only");
   const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);
   {
     const char* b0 = (const char*)B;
@@ -805,6 +852,7 @@ kx_status kron_solve(kx_plan p, const void* B, int64_t ldb, void* X, int64_t ldx
     if (b0 < x1 && x0 < b1) return fail(KX_EINVAL, "kron_solve: B and X overlap");
   }
   hipStream_t s = (hipStream_t)stream;
+  if (path == KX_PATH_SLICEWISE) return kron_solve_slicewise(p, (const double*)B, ldb, (double*)X, ldx, nrhs, s);
   SliceArgs A{};
   A.n1 = p->n[0]; A.n2 = p->n[1]; A.n3 = p->n[2]; A.n12 = p->n12; A.N = p->N;
   A.npairs = nrhs; A.n_occ = 1;

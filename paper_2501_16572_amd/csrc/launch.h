@@ -93,6 +93,11 @@ hipError_t launch_ace_factor(bool cplx, int n, void* S, void* U, void* X, int* i
 hipError_t launch_ace_tsmm(bool cplx, int64_t K, int m, int n, const void* A, int64_t lda, const void* B,
                            double alpha, double beta, void* C, int64_t ldc, const int* info, hipStream_t s);
 
+// C(m x n) = A(m x k) B(k x n), FP64 column-major: one small GEMM of the
+// slice-wise (Sec. II.A) solve.
+hipError_t launch_gemm_nn_f64(int m, int n, int k, const double* A, int64_t lda, const double* B, int64_t ldb,
+                              double* C, int64_t ldc, hipStream_t s);
+
 // Number of compute units of the current device (cached).
 int device_cu_count();
 

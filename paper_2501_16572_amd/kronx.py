@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "KX_OK", 1: "KX_EINVAL", 2: "KX_EUNSUPPORTED", 3: "KX_ENOMEM"
                 4: "KX_EDEVICE", 5: "KX_ESTATE"}
 BC = {"periodic": 0, "dirichlet": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
-PATH = {"fused": 0, "plain": 1}
+PATH = {"fused": 0, "plain": 1, "slicewise": 2}
 FLAG_COMPLEX = 16
 
 # Every symbol declared in include/kronx.h.

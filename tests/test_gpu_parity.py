@@ -46,7 +46,7 @@ SOLVE_CASES = [
 
 
 @pytest.mark.parametrize("case", range(len(SOLVE_CASES)))
-@pytest.mark.parametrize("path", ["fused", "plain"])
+@pytest.mark.parametrize("path", ["fused", "plain", "slicewise"])
 def test_kron_solve_fp64(kx, case, path):
     n, h, bc, omega = SOLVE_CASES[case]
     say("kron_solve fp64", n, bc, omega, path)
@@ -63,6 +63,20 @@ def test_kron_solve_fp64(kx, case, path):
         plan.destroy()
     ref = S.solve(B)
     assert rel_fro(X, ref) < 1e-12
+
+
+def test_slicewise_path_is_fp64_real_only(kx):
+    # the slice-wise comparison path exists for real FP64 plans only: other
+    # plans are refused before any device work
+    for prec, cplx in (("fp32", False), ("fp64", True)):
+        plan = kx.kron_setup((8, 8, 8), (0.3,) * 3, BCP, 12, 0.0, prec=prec, complex=cplx)
+        try:
+            dt = {("fp32", False): torch.float32, ("fp64", True): torch.complex128}[(prec, cplx)]
+            B = torch.zeros((1, 512), dtype=dt, device="cuda")
+            with pytest.raises(kx.KronxError, match="UNSUPPORTED"):
+                kx.kron_solve(plan, B, path="slicewise")
+        finally:
+            plan.destroy()
 
 
 @pytest.mark.parametrize("case", [0, 1, 3])
