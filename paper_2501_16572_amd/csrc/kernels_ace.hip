@@ -365,8 +365,10 @@ __global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, cons
 // factorization step); the matrix itself never goes through LDS.
 //
 // Factorization, right-looking without square roots inside the loop: step j
-// subtracts A_ij conj(A_kj) / A_jj from the trailing triangle (j < k <= i);
-// afterwards l_ij = A_ij / sqrt(A_jj), l_jj = sqrt(A_jj).
+// subtracts A_ij conj(A_kj) / A_jj from the trailing triangle (j < k <= i),
+// taken in panels of 8 columns (within a panel by one wave, then one rank-8
+// update of the later columns); afterwards l_ij = A_ij / sqrt(A_jj),
+// l_jj = sqrt(A_jj).
 // Inverse, in place, columns right to left (X_22 = inverse of the trailing
 // block, already in place):
 //   x_jj = 1/l_jj,  x_(j+1:, j) = -X_22 l_(j+1:, j) / l_jj,
@@ -380,9 +382,15 @@ __global__ void __launch_bounds__(1024) k_chol_inv_reg(int n, const T* __restric
                                                        int ldu, int* info, int base) {
   if (base > 0 && *info) return;
   constexpr int KT = 16;
-  __shared__ T col[2][128];
-  __shared__ T red[8][128];
+  constexpr int RHD = sizeof(T) > 8 ? 4 : 8;
+  __shared__ T pan[2][128][9];      // panel of 8 columns (pitch 9)
+  __shared__ T red2[8][128][RHD];   // per-group partial sums of the inverse
+  __shared__ T tl[128][8];          // T = Y22 L21 (and the pivots)
+  __shared__ T y11[8][8];           // inverse of the diagonal 8 x 8 block
+  __shared__ double pan_inv[2][8];  // 1 / pivot of the panel's columns
+  __shared__ int pan_bad;
   const int tid = threadIdx.x, i = tid & 127, grp = tid >> 7;
+  if (tid == 0) pan_bad = 0;
   const bool live = i < n;
   T a[KT];
 #pragma unroll
@@ -408,81 +416,159 @@ __global__ void __launch_bounds__(1024) k_chol_inv_reg(int n, const T* __restric
     a[0] = l;
   };
   const int nblk = (n + 7) / 8;
-  int bad = 0, buf = 0;
-  for (int jb = 0; jb < nblk && !bad; ++jb) {  // R = jb here
-    for (int jr = 0; jr < 8; ++jr) {
-      const int j = 8 * jb + jr;
-      if (j >= n) break;
-      if (grp == jr && live && i >= j) col[buf][i] = a[0];
-      __syncthreads();
-      const double d = real_(col[buf][j]);
-      if (!(d > 0.0)) {  // every thread reads the same value: a uniform exit
-        bad = j + 1;
-        break;
-      }
-      if (live && i > j) {
-        const T lij = scale_(1.0 / d, col[buf][i]);
+  int buf = 0;
+  // Factorization in panels of 8 columns (block jb in slot 0):
+  //  (1) the rows >= 8 jb publish the panel to LDS;
+  //  (2) wave 0 eliminates within the panel (8 column steps, two rows per
+  //      lane, no barrier: one wave's LDS accesses stay in program order);
+  //  (3) every thread takes its factored panel value back and applies the
+  //      panel's 8 rank-1 updates to its later columns at once.
+  for (int jb = 0; jb < nblk; ++jb) {  // R = jb here
+    if (live && i >= 8 * jb) pan[buf][i][grp] = a[0];
+    __syncthreads();
+    if (tid < 64) {
+      for (int jr = 0; jr < 8; ++jr) {
+        const int j = 8 * jb + jr;
+        if (j >= n) break;
+        const double d = real_(pan[buf][j][jr]);
+        if (!(d > 0.0)) {  // the same value in every lane: uniform
+          if (tid == 0) pan_bad = j + 1;
+          break;
+        }
+        const double inv = 1.0 / d;
+        if (tid == 0) pan_inv[buf][jr] = inv;
 #pragma unroll
-        for (int t = 0; t < KT; ++t) {
-          const int k = grp + 8 * ((t + jb) & (KT - 1));
-          if (k > j && k <= i) a[t] = sub_(a[t], mul_(lij, conj_(col[buf][k])));
+        for (int h = 0; h < 2; ++h) {
+          const int r = j - jr + tid + 64 * h;  // rows 8 jb + lane, + 64
+          if (r > j && r < n) {
+            const T lr = scale_(inv, pan[buf][r][jr]);
+            for (int c = jr + 1; c < 8; ++c)
+              pan[buf][r][c] = sub_(pan[buf][r][c], mul_(lr, conj_(pan[buf][j - jr + c][jr])));
+          }
         }
       }
-      buf ^= 1;
+    }
+    __syncthreads();
+    if (pan_bad) {
+      if (tid == 0) *info = pan_bad + base;
+      return;
+    }
+    if (live && i >= 8 * jb) a[0] = pan[buf][i][grp];
+    if (live && i >= 8 * (jb + 1)) {
+      // the panel's columns in two halves of four (register budget)
+#pragma unroll
+      for (int h = 0; h < 8; h += 4) {
+        T li[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) li[r] = scale_(pan_inv[buf][h + r], pan[buf][i][h + r]);
+#pragma unroll
+        for (int t = 1; t < KT; ++t) {
+          const int k = grp + 8 * (jb + t);
+          if (t < nblk - jb && k <= i) {
+            T v = a[t];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v = sub_(v, mul_(li[r], conj_(pan[buf][k][h + r])));
+            a[t] = v;
+          }
+        }
+      }
     }
     rot_left();
-  }
-  if (bad) {
-    if (tid == 0) *info = bad + base;
-    return;
+    buf ^= 1;
   }
   int R = nblk & (KT - 1);
   // l_ij = A_ij / sqrt(A_jj): publish the pivots, then scale
 #pragma unroll
   for (int t = 0; t < KT; ++t)
-    if (live && grp + 8 * ((t + R) & (KT - 1)) == i) red[0][i] = a[t];
+    if (live && grp + 8 * ((t + R) & (KT - 1)) == i) tl[i][0] = a[t];
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
     const int k = grp + 8 * ((t + R) & (KT - 1));
     if (live && k <= i) {
-      const double sd = sqrt(real_(red[0][k]));
+      const double sd = sqrt(real_(tl[k][0]));
       if (k == i) a[t] = from_real_(sd, zero_<T>());
       else a[t] = scale_(1.0 / sd, a[t]);
     }
   }
   __syncthreads();
-  // in-place inverse, columns right to left, the current block in slot 0
+  // In-place inverse by panels of 8 columns, right to left (the current
+  // panel in slot 0, Y22 = the inverse of the trailing block in slots >= 1):
+  //   Y11 = L11^{-1} (one lane per column, from the published panel),
+  //   T = Y22 L21 (partial sums per group, added in group order),
+  //   Y21 = -T Y11.
+  constexpr int RH = sizeof(T) > 8 ? 4 : 8;  // panel columns per partial-sum round
   for (int jb = nblk - 1; jb >= 0; --jb) {
     rot_right();  // R = jb
-    for (int jr = 7; jr >= 0; --jr) {
-      const int j = 8 * jb + jr;
-      if (j >= n) continue;
-      if (grp == jr && live && i >= j) col[buf][i] = a[0];
-      __syncthreads();
-      const double ljj = real_(col[buf][j]);
-      if (live && i > j) {
-        T sum = zero_<T>();
+    const int j0 = 8 * jb;
+    if (live && i >= j0) pan[buf][i][grp] = a[0];
+    __syncthreads();
+    if (tid < 8) {  // column c = tid of Y11, forward substitution
+      const int c = tid;
+      if constexpr (sizeof(T) == 8) {  // real: the column in registers
+        T y[8];
 #pragma unroll
-        for (int t = 0; t < KT; ++t) {
-          const int k = grp + 8 * ((t + jb) & (KT - 1));
-          if (k > j && k <= i) sum = fma_(a[t], col[buf][k], sum);
-        }
-        red[grp][i] = sum;
-      }
-      __syncthreads();
-      if (grp == jr && live && i >= j) {
-        if (i == j) {
-          a[0] = from_real_(1.0 / ljj, zero_<T>());
-        } else {
-          T sum = red[0][i];
+        for (int r = 0; r < 8; ++r) {
+          T v = zero_<T>();
+          if (j0 + r < n && r >= c) {
+            if (r == c) v = one_<T>();
 #pragma unroll
-          for (int g = 1; g < 8; ++g) sum = add_(sum, red[g][i]);
-          a[0] = scale_(-1.0 / ljj, sum);
+            for (int q = 0; q < r; ++q)
+              if (q >= c) v = sub_(v, mul_(pan[buf][j0 + r][q], y[q]));
+            v = scale_(1.0 / real_(pan[buf][j0 + r][r]), v);
+          }
+          y[r] = v;
+          y11[r][c] = v;
+        }
+      } else {  // complex: through LDS (register budget)
+        for (int r = 0; r < 8; ++r) {
+          T v = zero_<T>();
+          if (j0 + r < n && r >= c) {
+            if (r == c) v = one_<T>();
+            for (int q = c; q < r; ++q) v = sub_(v, mul_(pan[buf][j0 + r][q], y11[q][c]));
+            v = scale_(1.0 / real_(pan[buf][j0 + r][r]), v);
+          }
+          y11[r][c] = v;
         }
       }
-      buf ^= 1;
     }
+    for (int h = 0; h < 8; h += RH) {
+      if (live && i >= j0 + 8) {
+        T p[RH];
+#pragma unroll
+        for (int r = 0; r < RH; ++r) p[r] = zero_<T>();
+#pragma unroll
+        for (int t = 1; t < KT; ++t) {
+          const int k = grp + 8 * (jb + t);
+          if (t < nblk - jb && k <= i) {
+#pragma unroll
+            for (int r = 0; r < RH; ++r) p[r] = fma_(a[t], pan[buf][k][h + r], p[r]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RH; ++r) red2[grp][i][r] = p[r];
+      }
+      __syncthreads();
+      if (live && i >= j0 + 8 && grp >= h && grp < h + RH) {
+        T v = red2[0][i][grp - h];
+#pragma unroll
+        for (int g = 1; g < 8; ++g) v = add_(v, red2[g][i][grp - h]);
+        tl[i][grp] = v;
+      }
+      __syncthreads();
+    }
+    if (live && i >= j0) {
+      T v = zero_<T>();
+      if (i < j0 + 8) {  // diagonal block: Y11
+        if (grp <= i - j0) v = y11[i - j0][grp];
+      } else {          // Y21 = -T Y11
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          if (r >= grp) v = sub_(v, mul_(tl[i][r], y11[r][grp]));
+      }
+      a[0] = v;
+    }
+    buf ^= 1;
   }
   R = 0;
   // U[k][i] = conj(X[i][k]) for k <= i, zero below the diagonal of U
