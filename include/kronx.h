@@ -280,7 +280,10 @@ kx_status kx_plan_tuning(kx_plan p, int out[7]);
 
 /* kx_ace_workspace_bytes -- workspace for ace_construct (n_phi = 0) or
  * ace_apply on n_phi trial orbitals, for N grid points and n_s orbitals
- * (1 <= n_s <= 1024).  Host only. */
+ * (1 <= n_s <= 1024).  A workspace sized with n_phi > 0 serves both calls.
+ * It holds the split-K partials of the Gram products (about 256 x 128 KiB,
+ * fixed by the sizes, not by the device) and the n_s x n_s matrices.  Host
+ * only. */
 kx_status kx_ace_workspace_bytes(int64_t N, int n_s, int n_phi, int cplx, int64_t* bytes);
 
 /* ace_construct -- the ACE operator of Sec. III.A from n_s orbitals Psi and
@@ -288,7 +291,8 @@ kx_status kx_ace_workspace_bytes(int64_t N, int n_s, int n_phi, int cplx, int64_
  * negative definite), -M = L L^H (lower Cholesky factor),
  * xi = W L^{-H} (N x n_s, written to d_xi; the operator is -xi xi^H dV).
  * d_info: one device int, set to 0, or to j+1 if the j-th pivot of -M is not
- * positive (then d_xi is left unspecified); read it after synchronizing. */
+ * positive (then d_xi is left unspecified); read it after synchronizing.
+ * Results are bitwise reproducible: every sum runs in a fixed order. */
 kx_status ace_construct(int64_t N, int n_s, int cplx, double dV, const void* d_psi, int64_t ld_psi,
                         const void* d_w, int64_t ld_w, void* d_xi, int64_t ld_xi, void* d_work,
                         int64_t work_bytes, int* d_info, void* stream);

@@ -201,7 +201,11 @@ def _cols(t, N, what):
 
 
 def kron_solve(plan, B, X=None, path="fused", stream=None):
-    """X = f(L) B for the rows of B (shape (nrhs, N)); returns X."""
+    """X = f(L) B for the rows of B (shape (nrhs, N)); returns X.
+
+    path: "fused" (three fused passes), "plain" (one kernel per step, FP64)
+    or "slicewise" (the original formalism of Sec. II.A, one GEMM launch per
+    frontal slice; FP64 real plans; the comparison point for batching)."""
     import torch
     if X is None:
         X = torch.empty_like(B)
