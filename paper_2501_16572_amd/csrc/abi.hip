@@ -1036,10 +1036,12 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
       p->tune_tv[i] = cand[c][0];
       p->tune_bpc[i] = cand[c][1];
     }
-    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first run warms up
+    // the first run warms up; the best of the next two counts (one timing
+    // per candidate let run-to-run noise of ~2 % pick a slower variant)
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
       e = timed_batch(p, d_psi, ld_psi, n_occ, d_occ, d_phi, ld_phi, cur, vx, p->N, ev, s);
       if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
-      if (e == hipSuccess && rep == 1) {
+      if (e == hipSuccess && rep >= 1) {
         for (int i = 0; i < 3; ++i) {
           float ms = 0.f;
           hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
