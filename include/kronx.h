@@ -281,7 +281,7 @@ kx_status kx_plan_tuning(kx_plan p, int out[7]);
 /* kx_ace_workspace_bytes -- workspace for ace_construct (n_phi = 0) or
  * ace_apply on n_phi trial orbitals, for N grid points and n_s orbitals
  * (1 <= n_s <= 1024).  A workspace sized with n_phi > 0 serves both calls.
- * It holds the split-K partials of the Gram products (about 256 x 128 KiB,
+ * It holds the split-K partials of the Gram products (about 512 x 128 KiB,
  * fixed by the sizes, not by the device) and the n_s x n_s matrices.  Host
  * only. */
 kx_status kx_ace_workspace_bytes(int64_t N, int n_s, int n_phi, int cplx, int64_t* bytes);

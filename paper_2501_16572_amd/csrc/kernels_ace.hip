@@ -81,8 +81,9 @@ __device__ __forceinline__ d4_t mfma64(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int GKB = 64;           // rows (doubles) of A and B staged per step
+constexpr int GKB = 32;           // rows (doubles) of A and B staged per step
 constexpr int GP = GKB + 2;       // LDS pitch (2 mod 32): conflict-free fragment reads
+constexpr int GBLOCKS = 512;      // Gram blocks to aim for: two per CU
 constexpr int GTILE = 128 * 128;  // doubles of one output tile's partial
 
 // Partial Gram tiles, split over K (in doubles: K2 = K or 2K).  A block of
@@ -92,7 +93,7 @@ constexpr int GTILE = 128 * 128;  // doubles of one output tile's partial
 // order (every store is a contiguous 512-byte wave line); k_gram_mfma_reduce
 // maps them back to (i, j).
 template <bool CPLX>
-__global__ void __launch_bounds__(256) k_gram_mfma(int64_t K2, int m, int n, const double* __restrict__ A,
+__global__ void __launch_bounds__(256, 2) k_gram_mfma(int64_t K2, int m, int n, const double* __restrict__ A,
                                                    int64_t lda2, const double* __restrict__ B, int64_t ldb2,
                                                    double* __restrict__ part, int64_t kc2) {
   constexpr int BN = CPLX ? 64 : 128, WN = BN / 2, NTJ = WN / 16, SETS = CPLX ? 2 : 1;
@@ -109,40 +110,35 @@ __global__ void __launch_bounds__(256) k_gram_mfma(int64_t K2, int m, int n, con
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < NTJ; ++b) acc[st][a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
-  // Loads are unconditional (row and column indices clamped into the
-  // matrices) so that no branch separates them from the MFMA loop; rows past
-  // the chunk and columns past m / n are zeroed when the slab goes to LDS.
-  double ra[LA], rb[LB];
-  auto fetch = [&](int64_t ks) {
+  // Each slab is loaded when it is needed (the other block on the CU keeps
+  // the matrix units busy meanwhile; a register prefetch would not fit two
+  // blocks' worth of registers), 16 elements per operand at a time.  Loads
+  // are unconditional, with row and column indices clamped into the
+  // matrices; rows past the chunk and columns past m / n are zeroed on the
+  // way to LDS.
+  auto stage = [&](const double* __restrict__ M, int64_t ldm, int c0, int cmax, double* S, int cnt,
+                   int64_t ks) {
+#pragma unroll 1
+    for (int r0 = 0; r0 < cnt; r0 += 16) {
+      double v[16];
 #pragma unroll
-    for (int r = 0; r < LA; ++r) {
-      const int e = tid + 256 * r, c = min(i0 + e / GKB, m - 1);
-      const int64_t k = min(ks + e % GKB, K2 - 1);
-      ra[r] = A[k + (int64_t)c * lda2];
-    }
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * (r0 + u), c = min(c0 + e / GKB, cmax - 1);
+        const int64_t k = min(ks + e % GKB, K2 - 1);
+        if (r0 + u < cnt) v[u] = M[k + (int64_t)c * ldm];
+      }
 #pragma unroll
-    for (int r = 0; r < LB; ++r) {
-      const int e = tid + 256 * r, c = min(j0 + e / GKB, n - 1);
-      const int64_t k = min(ks + e % GKB, K2 - 1);
-      rb[r] = B[k + (int64_t)c * ldb2];
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * (r0 + u);
+        const bool ok = ks + e % GKB < k1 && c0 + e / GKB < cmax;
+        if (r0 + u < cnt) S[(e / GKB) * GP + e % GKB] = ok ? v[u] : 0.0;
+      }
     }
   };
-  fetch(k0);
   for (int64_t ks = k0; ks < k1; ks += GKB) {
-#pragma unroll
-    for (int r = 0; r < LA; ++r) {
-      const int e = tid + 256 * r;
-      const bool ok = ks + e % GKB < k1 && i0 + e / GKB < m;
-      As[(e / GKB) * GP + e % GKB] = ok ? ra[r] : 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < LB; ++r) {
-      const int e = tid + 256 * r;
-      const bool ok = ks + e % GKB < k1 && j0 + e / GKB < n;
-      Bs[(e / GKB) * GP + e % GKB] = ok ? rb[r] : 0.0;
-    }
+    stage(A, lda2, i0, m, As, LA, ks);
+    stage(B, ldb2, j0, n, Bs, LB, ks);
     __syncthreads();
-    if (ks + GKB < k1) fetch(ks + GKB);
 #pragma unroll
     for (int s4 = 0; s4 < GKB / 4; ++s4) {
       const int kk = 4 * s4 + lg;
@@ -656,7 +652,7 @@ __global__ void k_conj_transpose(int m, int n, const T* __restrict__ src, int ld
   }
 }
 
-// Split-K chunk count of a Gram product: about one block per compute unit
+// Split-K chunk count of a Gram product: about two blocks per compute unit
 // over all output tiles, chunks a multiple of GKB doubles long.
 struct GramShape {
   int tiles_m, tiles_n, chunks;
@@ -668,7 +664,7 @@ GramShape gram_shape(bool cplx, int64_t K, int m, int n) {
   g.tiles_n = (n + (cplx ? 63 : 127)) / (cplx ? 64 : 128);
   const int64_t K2 = cplx ? 2 * K : K;
   const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
-  int64_t chunks = std::max<int64_t>(1, 256 / tiles);
+  int64_t chunks = std::max<int64_t>(1, GBLOCKS / tiles);
   chunks = std::min<int64_t>(chunks, (K2 + GKB - 1) / GKB);
   g.kc2 = ((K2 + chunks - 1) / chunks + GKB - 1) / GKB * GKB;
   g.chunks = (int)((K2 + g.kc2 - 1) / g.kc2);

@@ -101,20 +101,20 @@ def test_null_plan_errors():
 
 def test_ace_workspace_size_and_argument_errors():
     # host-only: the workspace formula (split-K partials of the MFMA Gram
-    # product: about 256 blocks over the 128 x 128 (complex 128 x 64) output
-    # tiles, chunks a multiple of 64 doubles, each chunk x tile a 128 KiB
+    # product: about 512 blocks over the 128 x 128 (complex 128 x 64) output
+    # tiles, chunks a multiple of 32 doubles, each chunk x tile a 128 KiB
     # partial; 256-byte aligned; plus the small n_s x n_s matrices) and EINVAL
     # before any device work
     def part_bytes(N, m, n, cplx):
         tiles = -(-m // 128) * -(-n // (64 if cplx else 128))
         K2 = N * (2 if cplx else 1)
-        chunks = min(max(1, 256 // tiles), -(-K2 // 64))
-        kc2 = -(-(-(-K2 // chunks)) // 64) * 64
+        chunks = min(max(1, 512 // tiles), -(-K2 // 32))
+        kc2 = -(-(-(-K2 // chunks)) // 32) * 32
         return -(-K2 // kc2) * tiles * 128 * 128 * 8
 
     align = lambda b: (b + 255) // 256 * 256
     N, ns = 373248, 128
-    assert part_bytes(N, ns, ns, False) == 254 * 128 * 1024   # 1472-row chunks
+    assert part_bytes(N, ns, ns, False) == 508 * 128 * 1024   # 736-row chunks
     assert kronx.kx_ace_workspace_bytes(N, ns, 0, False) == align(part_bytes(N, ns, ns, False)) + align(
         (3 * ns * ns + ns) * 8)
     for (N, ns, nphi, cplx) in [(373248, 128, 200, True), (2145, 140, 130, False), (2145, 6, 5, True),
