@@ -14,7 +14,8 @@
 //          reproducible results);
 //   tsmm:  C(K x n) = beta * C + alpha * A(K x m) B(m x n).
 // The Cholesky factorization and the triangular inverse of the n_s x n_s
-// matrix run in one workgroup, in LDS where the matrix fits.
+// matrix run in one workgroup with the matrix in registers (n_s <= 128), or
+// tile by tile (128-tiles, small GEMM updates) for larger n_s.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -60,8 +61,6 @@ __device__ __forceinline__ double from_real_(double v, double) { return v; }
 __device__ __forceinline__ Z from_real_(double v, Z) { return Z{v, 0.0}; }
 __device__ __forceinline__ double real_(double a) { return a; }
 __device__ __forceinline__ double real_(Z a) { return a.re; }
-__device__ __forceinline__ double abs2_(double a) { return a * a; }
-__device__ __forceinline__ double abs2_(Z a) { return a.re * a.re + a.im * a.im; }
 
 // ---------------------------------------------------------------------------
 // MFMA forms (v_mfma_f64_16x16x4).  Operand layout, lane l = 16*lg + lr:
