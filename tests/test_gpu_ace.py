@@ -109,6 +109,43 @@ def test_ace_ragged_grid_and_large_orbital_sets(kx, kind, ns):
         assert rel_fro(to_host(vphi), ref) < 1e-11, n_phi
 
 
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_ace_padded_leading_dimensions(kx, kind):
+    # every orbital set as a view with leading dimension N + 37: the padding of
+    # the inputs holds NaN (any read past N would poison the result) and the
+    # padding of the outputs a sentinel that must survive
+    n, h, ns, n_phi, pad = (15, 13, 11), (0.4, 0.4, 0.4), 70, 9, 37
+    N = n[0] * n[1] * n[2]
+    say("ace padded ld", kind)
+    if kind == "real":
+        psi = random_orbitals(n, h, ns, seed=95)
+    else:
+        L = [n[d] * h[d] for d in range(3)]
+        psi = random_orbitals(n, h, ns, seed=95, kpt=(2 * np.pi / L[0] * 0.25, 0.0, 0.0), decay=2.0)
+    dV = float(np.prod(h))
+    rng = np.random.default_rng(95)
+    B = rng.standard_normal((ns, ns)) / np.sqrt(ns)
+    W = np.ascontiguousarray(-(psi.T @ (B @ B.T + np.eye(ns))).T)
+    phi = rng.standard_normal((n_phi, N)) * (1 + (1j if kind == "complex" else 0))
+    v0 = rng.standard_normal((n_phi, N)) * (1 + (1j if kind == "complex" else 0))
+    ct = torch.float64 if kind == "real" else torch.complex128
+
+    def padded(a, fill):
+        t = torch.full((a.shape[0], N + pad), fill, dtype=ct, device="cuda")
+        t[:, :N] = to_dev(a, ct)
+        return t
+
+    P, Wt, Ph = padded(psi, float("nan")), padded(W, float("nan")), padded(phi, float("nan"))
+    X, V = padded(np.zeros_like(W), 7.0), padded(v0, 7.0)
+    kx.ace_construct(P[:, :N], Wt[:, :N], dV, xi=X[:, :N])
+    kx.ace_apply(X[:, :N], Ph[:, :N], dV, V[:, :N])
+    torch.cuda.synchronize()
+    xi_ref = ace_construct(psi, W, dV)
+    assert rel_fro(to_host(X[:, :N]), xi_ref) < 1e-12
+    assert rel_fro(to_host(V[:, :N]), v0 + ace_apply(xi_ref, phi, dV)) < 1e-12
+    assert bool((X[:, N:] == 7.0).all()) and bool((V[:, N:] == 7.0).all())
+
+
 def test_device_chain_reproduces_w(kx):
     # W = Vx Psi from exx_apply, then ACE from it: the compressed operator
     # returns W on the orbitals
