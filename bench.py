@@ -147,7 +147,8 @@ def run_ace(kx, torch, psi_d, w_d, dV, args):
     FP64 contractions over the grid (2 N n_s^2 flops each against 16 N n_s
     bytes), so they are priced against the FP64 matrix peak as well as HBM."""
     n_s, N = psi_d.shape
-    work = torch.empty(kx.kx_ace_workspace_bytes(N, n_s, n_s, False) // 8 + 64, dtype=torch.float64,
+    cplx = psi_d.is_complex()
+    work = torch.empty(kx.kx_ace_workspace_bytes(N, n_s, n_s, cplx) // 8 + 64, dtype=torch.float64,
                        device="cuda")
     xi = kx.ace_construct(psi_d, w_d, dV, work=work)
     v = torch.zeros_like(psi_d)
@@ -165,16 +166,19 @@ def run_ace(kx, torch, psi_d, w_d, dV, args):
     ev[2].record()
     torch.cuda.synchronize()
     tc, ta = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
-    mat = N * n_s * 8
-    flops = 2 * (2.0 * N * n_s * n_s)              # Gram + tall-skinny product, each 2 N n_s^2
-    return dict(n_s=n_s, N=N, construct_ms=round(tc, 4), apply_ms=round(ta, 4),
+    mat = N * n_s * (16 if cplx else 8)
+    # Gram + tall-skinny product, each 2 N n_s^2 real flops (a complex
+    # multiply-add is 4 real ones)
+    flops = 2 * (2.0 * N * n_s * n_s) * (4 if cplx else 1)
+    return dict(n_s=n_s, N=N, dtype="c128" if cplx else "f64", construct_ms=round(tc, 4), apply_ms=round(ta, 4),
                 construct_tflops=round(flops / tc / 1e9, 2), apply_tflops=round(flops / ta / 1e9, 2),
                 fp64_mfma_peak_tflops=78.6,
                 construct_gbs=round(3 * mat / tc / 1e6, 1), apply_gbs=round(4 * mat / ta / 1e6, 1),
                 hbm_peak_gbs=8000.0, reproduces_w_rel_err=err,
-                note="flops: Gram 2 N n_s^2 + product 2 N n_s^2 per call; algorithmic bytes: construct "
-                     "reads Psi, W and writes xi (3 N n_s 8 B), apply reads xi, Phi and reads+writes "
-                     "V Phi (4 N n_s 8 B); construct also factors and inverts the n_s x n_s matrix")
+                note="flops: Gram 2 N n_s^2 + product 2 N n_s^2 real flops per call (x4 complex); "
+                     "algorithmic bytes: construct reads Psi, W and writes xi (3 N n_s elements), apply "
+                     "reads xi, Phi and reads+writes V Phi (4 N n_s elements), 8 B real / 16 B complex; "
+                     "construct also factors and inverts the n_s x n_s matrix")
 
 
 def run_batched(kx, torch, np, cfg, args):
@@ -268,6 +272,16 @@ def run_batched(kx, torch, np, cfg, args):
                        sample=f"2 target bands x {sy['n_occ']} occupied of the {sy['n']} system, "
                               f"FP64 NumPy, 1 thread, {dt:.1f} s (its solves are the cheapest "
                               f"of the batch)")
+        # ACE at a k-point: complex128 orbitals of k-point 0 and W = their Vx
+        # from the batched call (scaled by the number of replays, which leaves
+        # the operator's action on the orbitals equal to W)
+        ace = None
+        if not args.no_ace:
+            log("ace at k-point 0")
+            try:
+                ace = run_ace(kx, torch, psi_k[0].to(torch.complex128), vx_k[0], float(np.prod(kg["h"])), args)
+            except kx.KronxError as exc:
+                ace = {"error": str(exc)}
     finally:
         for p in plans.values():
             p.destroy()
@@ -286,6 +300,7 @@ def run_batched(kx, torch, np, cfg, args):
         "rel_err_sampled_vs_oracle": sample_err,
         "roofline": None,
         "cpu_baseline": cpu,
+        "ace_kpoint": ace,
     }
     print(json.dumps(line), flush=True)
 
