@@ -215,14 +215,16 @@ __global__ void __launch_bounds__(256) k_gram_mfma_reduce(int chunks, int tiles_
 // columns) stays in LDS for the whole launch; A is read straight from global
 // memory into fragment registers, one group of 8 steps ahead.  Each wave owns
 // 32-row tiles of C, taken in a grid stride.  Skipped when info && *info.
-constexpr int TQ = 258;  // LDS pitch (doubles) of the B tile: 2 mod 32
+constexpr int TQ = 258;     // LDS pitch (doubles) of the B tile: 2 mod 32
+constexpr int TS_TT = 1;     // 16-row accumulator tiles per wave tile
+constexpr int TS_WPB = 8;    // waves per block: two per SIMD beside the LDS-resident B
 template <bool CPLX>
-__global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, const double* __restrict__ A,
+__global__ void __launch_bounds__(64 * TS_WPB) k_tsmm_mfma(int64_t K, int m, int n, const double* __restrict__ A,
                                                    int64_t lda, const double* __restrict__ B, int ldb,
                                                    double alpha, double beta, double* C, int64_t ldc,
                                                    const int* info) {
   if (info && *info) return;
-  constexpr int NJ = CPLX ? 64 : 128, NTJ = 4, SETS = CPLX ? 2 : 1, G = 8;
+  constexpr int NJ = CPLX ? 64 : 128, NTJ = 4, SETS = CPLX ? 2 : 1, G = 4;
   constexpr int PITCH = CPLX ? TQ : 130;
   __shared__ double Xs[NJ * PITCH];
   const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
@@ -231,26 +233,27 @@ __global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, cons
   const int QS = (Q + 3) / 4;      // 4-deep steps (the last group may run past QS)
   const int j0 = blockIdx.y * NJ;
   // X[j][q] = B as doubles: column j of B is contiguous in q
-  for (int e = tid; e < NJ * PITCH; e += 256) {
+  for (int e = tid; e < NJ * PITCH; e += 64 * TS_WPB) {
     const int j = e / PITCH, q = e % PITCH;
     Xs[e] = (q < Q && j0 + j < n) ? B[q + (int64_t)(j0 + j) * (CPLX ? 2 * ldb : ldb)] : 0.0;
   }
   __syncthreads();
-  const int tiles = (int)((K + 31) / 32);
-  const int wstride = gridDim.x * 4;
+  constexpr int ROWS = 16 * TS_TT;  // rows of C per wave tile
+  const int tiles = (int)((K + ROWS - 1) / ROWS);
+  const int wstride = gridDim.x * TS_WPB;
   // real: the wave covers all 128 columns in 8 tiles, one set; complex: 64
   // columns in 4 tiles, two sets (Re, Im)
   constexpr int TJ = CPLX ? 4 : 8;
-  d4_t acc[SETS][TJ][2];
-  double y[2][G], yn[2][G];
+  d4_t acc[SETS][TJ][TS_TT];
+  double y[TS_TT][G], yn[TS_TT][G];
   const int ngroups = (QS + G - 1) / G;
   // Unconditional loads with clamped indices, so that no branch separates
   // them from the MFMA loop: rows past K produce results that are not stored,
   // contraction indices past Q meet zero rows of X.
-  auto load = [&](double (&dst)[2][G], int tile, int grp) {
+  auto load = [&](double (&dst)[TS_TT][G], int tile, int grp) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int64_t k = min((int64_t)tile * 32 + 16 * t + lr, K - 1);
+    for (int t = 0; t < TS_TT; ++t) {
+      const int64_t k = min((int64_t)tile * ROWS + 16 * t + lr, K - 1);
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int q = 4 * (grp * G + u) + lg;
@@ -265,7 +268,7 @@ __global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, cons
       }
     }
   };
-  int tile = blockIdx.x * 4 + w;
+  int tile = blockIdx.x * TS_WPB + w;
   if (tile >= tiles) return;
   load(y, tile, 0);
   for (;;) {
@@ -274,7 +277,7 @@ __global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, cons
 #pragma unroll
       for (int a = 0; a < TJ; ++a)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[st][a][t] = d4_t{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < TS_TT; ++t) acc[st][a][t] = d4_t{0.0, 0.0, 0.0, 0.0};
     for (int grp = 0; grp < ngroups; ++grp) {
       // prefetch the next group of this wave's sequence (past the last tile:
       // a clamped, harmless reload of the last one)
@@ -299,32 +302,32 @@ __global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, cons
 #pragma unroll
         for (int a = 0; a < TJ; ++a)
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
+          for (int t = 0; t < TS_TT; ++t) {
             acc[0][a][t] = mfma64(x0[a], y[t][u], acc[0][a][t]);
             if (CPLX) acc[SETS - 1][a][t] = mfma64(x1[a], y[t][u], acc[SETS - 1][a][t]);
           }
       }
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+      for (int t = 0; t < TS_TT; ++t)
 #pragma unroll
         for (int u = 0; u < G; ++u) y[t][u] = yn[t][u];
     }
-    // tile done: D[j][k], j = j0 + 16a + lg + 4r, k = 32 tile + 16t + lr.
+    // tile done: D[j][k], j = j0 + 16a + lg + 4r, k = ROWS tile + 16t + lr.
     // With beta != 0 the old values of C are loaded for two j-tiles at a
     // time before any of them is stored (a load after a store to C cannot
     // be hoisted by the compiler, which would serialize every update).
 #pragma unroll
     for (int a0 = 0; a0 < TJ; a0 += 2) {
-      double old[2][2][4][SETS];
+      double old[2][TS_TT][4][SETS];
       if (beta != 0.0) {
 #pragma unroll
         for (int da = 0; da < 2; ++da)
 #pragma unroll
-          for (int t = 0; t < 2; ++t)
+          for (int t = 0; t < TS_TT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int j = min(j0 + 16 * (a0 + da) + lg + 4 * r, n - 1);
-              const int64_t k = min((int64_t)tile * 32 + 16 * t + lr, K - 1);
+              const int64_t k = min((int64_t)tile * ROWS + 16 * t + lr, K - 1);
 #pragma unroll
               for (int st = 0; st < SETS; ++st) old[da][t][r][st] = C[(k + (int64_t)j * ldc) * SETS + st];
             }
@@ -332,11 +335,11 @@ __global__ void __launch_bounds__(256) k_tsmm_mfma(int64_t K, int m, int n, cons
 #pragma unroll
       for (int da = 0; da < 2; ++da)
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < TS_TT; ++t)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int j = j0 + 16 * (a0 + da) + lg + 4 * r;
-            const int64_t k = (int64_t)tile * 32 + 16 * t + lr;
+            const int64_t k = (int64_t)tile * ROWS + 16 * t + lr;
             if (k < K && j < n) {
 #pragma unroll
               for (int st = 0; st < SETS; ++st) {
@@ -782,8 +785,8 @@ hipError_t launch_ace_tsmm(bool cplx, int64_t K, int m, int n, const void* A, in
   if (K <= 0 || m <= 0 || n <= 0) return hipSuccess;
   // contraction slabs of at most 128 (B's column tile must fit in LDS);
   // slabs after the first accumulate
-  const int64_t tiles = (K + 31) / 32;
-  const int bx = (int)std::min<int64_t>((tiles + 3) / 4, device_cu_count());
+  const int64_t tiles = (K + 16 * TS_TT - 1) / (16 * TS_TT);
+  const int bx = (int)std::min<int64_t>((tiles + TS_WPB - 1) / TS_WPB, device_cu_count());
   const int nj = cplx ? 64 : 128;
   const int64_t f = cplx ? 2 : 1;  // doubles per element
   dim3 grid(bx, (n + nj - 1) / nj);
@@ -793,10 +796,10 @@ hipError_t launch_ace_tsmm(bool cplx, int64_t K, int m, int n, const void* A, in
     const double* Bs = (const double*)B + f * q0;
     const double bq = q0 == 0 ? beta : 1.0;
     if (cplx)
-      hipLaunchKernelGGL(k_tsmm_mfma<true>, grid, dim3(256), 0, s, K, mq, n, As, lda, Bs, m, alpha, bq, (double*)C,
+      hipLaunchKernelGGL(k_tsmm_mfma<true>, grid, dim3(64 * TS_WPB), 0, s, K, mq, n, As, lda, Bs, m, alpha, bq, (double*)C,
                          ldc, info);
     else
-      hipLaunchKernelGGL(k_tsmm_mfma<false>, grid, dim3(256), 0, s, K, mq, n, As, lda, Bs, m, alpha, bq,
+      hipLaunchKernelGGL(k_tsmm_mfma<false>, grid, dim3(64 * TS_WPB), 0, s, K, mq, n, As, lda, Bs, m, alpha, bq,
                          (double*)C, ldc, info);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
