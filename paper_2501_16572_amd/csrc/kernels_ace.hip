@@ -435,13 +435,40 @@ __global__ void __launch_bounds__(1024) k_chol_inv_reg(int n, const T* __restric
         }
         const double inv = 1.0 / d;
         if (tid == 0) pan_inv[buf][jr] = inv;
+        // rows 8 jb + lane and 8 jb + lane + 64
+        if constexpr (sizeof(T) == 8) {
+          // real: all operands loaded before the updates (one LDS round trip
+          // per step)
+          T lr[2], prow[2][8], pcol[8];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int r = j - jr + tid + 64 * h;  // rows 8 jb + lane, + 64
-          if (r > j && r < n) {
-            const T lr = scale_(inv, pan[buf][r][jr]);
-            for (int c = jr + 1; c < 8; ++c)
-              pan[buf][r][c] = sub_(pan[buf][r][c], mul_(lr, conj_(pan[buf][j - jr + c][jr])));
+          for (int c = 0; c < 8; ++c)
+            if (c > jr) pcol[c] = pan[buf][j - jr + c][jr];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int r = min(j - jr + tid + 64 * h, 127);
+            lr[h] = scale_(inv, pan[buf][r][jr]);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+              if (c > jr) prow[h][c] = pan[buf][r][c];
+          }
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int r = j - jr + tid + 64 * h;
+            if (r > j && r < n) {
+#pragma unroll
+              for (int c = 0; c < 8; ++c)
+                if (c > jr) pan[buf][r][c] = sub_(prow[h][c], mul_(lr[h], conj_(pcol[c])));
+            }
+          }
+        } else {  // complex: row by row (register budget)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int r = j - jr + tid + 64 * h;
+            if (r > j && r < n) {
+              const T lr = scale_(inv, pan[buf][r][jr]);
+              for (int c = jr + 1; c < 8; ++c)
+                pan[buf][r][c] = sub_(pan[buf][r][c], mul_(lr, conj_(pan[buf][j - jr + c][jr])));
+            }
           }
         }
       }
