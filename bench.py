@@ -419,9 +419,9 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the exchange path of this library is a "
-              "single-device build (see the sharding notes in DESIGN.md); use --gpus 1.",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: the exchange path of this library is "
+              "single-device (band and k-point sharding across GPUs is not implemented); "
+              "use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
