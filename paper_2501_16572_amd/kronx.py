@@ -195,9 +195,12 @@ def kron_destroy(plan):
 
 
 def _cols(t, N, what):
-    if t.dim() != 2 or t.stride(1) != 1 or t.shape[1] < N:
+    if t.dim() != 2 or (t.stride(1) != 1 and t.shape[1] > 1) or t.shape[1] < N:
         raise ValueError(f"{what}: expected a (ncols, >=N) tensor with unit stride along the grid")
-    return t.data_ptr(), t.stride(0)
+    # with a single column the row stride is arbitrary (torch and numpy may
+    # report any value for a dimension of size 1): N is a valid leading dimension
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.stride(0), N)
+    return t.data_ptr(), ld
 
 
 def kron_solve(plan, B, X=None, path="fused", stream=None):

@@ -70,7 +70,7 @@ def test_ace_matches_oracle(kx, kind, nb):
 
 
 @pytest.mark.parametrize("kind", ["real", "complex"])
-@pytest.mark.parametrize("ns", [6, 70, 128, 140, 260])
+@pytest.mark.parametrize("ns", [1, 6, 70, 128, 140, 260])
 def test_ace_ragged_grid_and_large_orbital_sets(kx, kind, ns):
     # N = 15*13*11 = 2145: ragged against the 32-row tiles and split-K chunks;
     # n_s = 128 fills one factorization tile exactly, 140 and 260 take the
