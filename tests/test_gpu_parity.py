@@ -266,6 +266,18 @@ def test_exx_deterministic_and_edge_cases(kx):
             kx.exx_apply(plan, bad, occ, psid, vx0)
         torch.cuda.synchronize()
         assert float(vx0.abs().max()) == 0.0
+        # one occupied orbital and one target, as (1, N) tensors whose row
+        # stride is not N (a size-1 dimension may carry any stride): the
+        # result equals the corresponding slice of the full computation
+        g1 = np.array([0.7])
+        p1 = to_dev(psi[0], torch.float64).as_strided((1, N), (1, 1))
+        assert p1.stride(0) == 1
+        vx1 = torch.zeros_like(p1)
+        kx.exx_apply(plan, p1, to_dev(g1, torch.float64), p1, vx1)
+        torch.cuda.synchronize()
+        S = KronSolver(n, h, BCP, 12, 0.106)
+        ref = vx_apply(psi[:1], g1, psi[:1], S)
+        assert rel_fro(to_host(vx1), ref) < 1e-12
     finally:
         plan.destroy()
 
