@@ -146,6 +146,29 @@ def test_ace_padded_leading_dimensions(kx, kind):
     assert bool((X[:, N:] == 7.0).all()) and bool((V[:, N:] == 7.0).all())
 
 
+@pytest.mark.parametrize("kind", ["real", "complex"])
+@pytest.mark.parametrize("n", [(4, 4, 4), (3, 5, 7)])
+def test_ace_tiny_grids(kx, kind, n):
+    # N = 64 and 105 grid points: fewer rows than one block's share, so most
+    # waves of the product kernel and most split-K chunks have no work
+    h, ns = (0.5, 0.5, 0.5), 5
+    N = n[0] * n[1] * n[2]
+    say("ace tiny", kind, n)
+    rng = np.random.default_rng(N)
+    A = rng.standard_normal((N, ns)) + (1j * rng.standard_normal((N, ns)) if kind == "complex" else 0)
+    dV = float(np.prod(h))
+    psi = np.ascontiguousarray((np.linalg.qr(A)[0] / np.sqrt(dV)).T)
+    B = rng.standard_normal((ns, ns)) / np.sqrt(ns)
+    W = np.ascontiguousarray(-(psi.T @ (B @ B.T + np.eye(ns))).T)
+    ct = torch.float64 if kind == "real" else torch.complex128
+    xi = kx.ace_construct(to_dev(psi, ct), to_dev(W, ct), dV)
+    v = torch.zeros_like(xi)
+    kx.ace_apply(xi, to_dev(psi, ct), dV, v)
+    torch.cuda.synchronize()
+    assert rel_fro(to_host(xi), ace_construct(psi, W, dV)) < 1e-12
+    assert rel_fro(to_host(v), W) < 1e-12
+
+
 def test_device_chain_reproduces_w(kx):
     # W = Vx Psi from exx_apply, then ACE from it: the compressed operator
     # returns W on the orbitals
