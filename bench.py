@@ -494,7 +494,10 @@ def main():
     head_vx, head_ex = results[f"{head[0]}_{head[1]}"]
     ace = None
     if "fp64_fused" in results and not args.no_ace:
-        ace = run_ace(kx, torch, psi_d, results["fp64_fused"][0], float(np.prod(cfg["h"])), args)
+        try:
+            ace = run_ace(kx, torch, psi_d, results["fp64_fused"][0], float(np.prod(cfg["h"])), args)
+        except kx.KronxError as exc:  # the benchmark line is printed regardless
+            ace = {"error": str(exc)}
 
     prec, path, r, t = head
     # roofline of the dominant kernel of the headline form (fused passes)
