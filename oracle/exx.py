@@ -81,21 +81,34 @@ def exchange_energy_pairs(psi, g, solver, dV):
     return E
 
 
-def vx_apply_kpoints(psi_k, occ_k, w_k, solver_for):
+def vx_apply_kpoints(psi_k, occ_k, w_k, kpts, make_solver):
     """Eq. (Vx:Poisson) over a k-point set (one spin channel).
 
-    psi_k: list over k of (n_b, N) Bloch orbitals; occ_k: list of (n_b,)
-    occupations g_nk (only g > 0 orbitals contribute as psi_mq); w_k: Brillouin
-    zone weights; solver_for(ik, iq): KronSolver at kappa = k - q.
-    Returns the list over k of Vx psi_nk, shape (n_b, N).
+    psi_k: list over k of (n_b, N) Bloch orbitals psi_nk(r) (the full Bloch
+    function on the cell's grid); occ_k: list of (n_b,) occupations g_nk;
+    w_k: Brillouin-zone weights; kpts: list of k vectors (bohr^-1);
+    make_solver(kappa): a KronSolver with Bloch vector kappa.
+
+    For the target k and every q, the pair density conj(psi_mq) psi_nk is a
+    Bloch function with wavevector k - q, so its Poisson problem is solved
+    under the Bloch condition at kappa = k - q (Sec. II); the source orbitals
+    are the occupied ones at q (g_mq > 0), weighted by w_q g_mq.  Returns the
+    list over k of Vx psi_nk, shape (n_b, N).
     """
     nk = len(psi_k)
     out = []
     for ik in range(nk):
         W = 0
         for iq in range(nk):
+            kappa = tuple(float(kpts[ik][d]) - float(kpts[iq][d]) for d in range(3))
             occ_mask = occ_k[iq] > 0
             w = w_k[iq] * occ_k[iq][occ_mask]
-            W = W + vx_apply(psi_k[iq][occ_mask], w, psi_k[ik], solver_for(ik, iq))
+            W = W + vx_apply(psi_k[iq][occ_mask], w, psi_k[ik], make_solver(kappa))
         out.append(W)
     return out
+
+
+def exchange_energy_kpoints(psi_k, occ_k, w_k, W_k, dV):
+    """E_x = sum_k w_k sum_n g_nk Re <psi_nk, W_nk> dV over a k-point set (R5)."""
+    return float(sum(w_k[ik] * exchange_energy(psi_k[ik], occ_k[ik], W_k[ik], dV)
+                     for ik in range(len(psi_k))))

@@ -12,7 +12,7 @@ checked through kx_batched_schedule so that grouping is known to happen.
 import numpy as np
 import pytest
 
-from oracle.exx import vx_apply_kpoints
+from oracle.exx import exchange_energy, vx_apply, vx_apply_kpoints
 from oracle.kron import KronSolver
 from paper_2501_16572_amd.workloads import fermi_occupations, random_orbitals
 
@@ -55,9 +55,10 @@ def test_kpoint_set_one_launch_per_round(kx, prec):
     L = [n[d] * h[d] for d in range(3)]
     kpts = [(2 * np.pi / L[0] * 0.25, 2 * np.pi / L[1] * 0.25, 0.0),
             (-2 * np.pi / L[0] * 0.25, 2 * np.pi / L[1] * 0.25, 0.0)]
-    wk = [0.5, 0.5]
+    wk = [0.375, 0.625]
     psi = [random_orbitals(n, h, 5, seed=80 + i, kpt=k, decay=2.0) for i, k in enumerate(kpts)]
-    g = [np.array([1.0, 1.0, 0.7, 0.0, 0.0])] * 2
+    g = [np.array([1.0, 0.85, 0.0, 0.0, 0.0]), np.array([1.0, 0.9, 0.45, 0.0, 0.0])]
+    nocc = [2, 3]
     ct = torch.complex128 if prec == "fp64" else torch.complex64
     if prec == "fp32":
         psi = [p.astype(np.complex64).astype(np.complex128) for p in psi]
@@ -73,8 +74,8 @@ def test_kpoint_set_one_launch_per_round(kx, prec):
                 kq = tuple(kpts[ik][d] - kpts[iq][d] for d in range(3))
                 plan = kx.kron_setup(n, h, BCP, 12, 0.0, kq=kq, prec=prec, complex=True)
                 plans.append(plan)
-                occ = to_dev(wk[iq] * g[iq][:3], torch.float64)
-                tasks.append(dict(plan=plan, psi=dev_psi[iq][:3], occ=occ, phi=dev_psi[ik], vx=vx[ik],
+                occ = to_dev(wk[iq] * g[iq][:nocc[iq]], torch.float64)
+                tasks.append(dict(plan=plan, psi=dev_psi[iq][:nocc[iq]], occ=occ, phi=dev_psi[ik], vx=vx[ik],
                                   ex=ex[ik], gphi=gphi))
         results = []
         for rep in range(2):
@@ -94,17 +95,18 @@ def test_kpoint_set_one_launch_per_round(kx, prec):
         assert np.array_equal(results[0][0][ik], results[1][0][ik])
         assert results[0][1][ik] == results[1][1][ik]
 
-    def solver_for(ik, iq):
-        kq = tuple(kpts[ik][d] - kpts[iq][d] for d in range(3))
-        return KronSolver(n, h, BCP, 12, 0.0, kq)
-
-    W = vx_apply_kpoints(psi, g, wk, solver_for)
-    tol = 1e-12 if prec == "fp64" else 1e-6
+    W = vx_apply_kpoints(psi, g, wk, kpts, lambda kq: KronSolver(n, h, BCP, 12, 0.0, kq))
+    dV = float(np.prod(h))
+    atoms = 2.0 * sum(wk[i] * g[i].sum() for i in range(2)) / 14.0
     out, exv = results[0]
     for ik in range(2):
-        assert rel_fro(out[ik], W[ik]) < tol, ik
-        Eref = wk[ik] * float(np.sum(g[ik] * np.real(np.sum(np.conj(psi[ik]) * W[ik], axis=1)))) * np.prod(h)
-        assert abs(exv[ik] - Eref) < 10 * tol * abs(Eref), (exv[ik], Eref)
+        Eref = wk[ik] * exchange_energy(psi[ik], g[ik], W[ik], dV)
+        if prec == "fp64":
+            assert rel_fro(out[ik], W[ik]) < 1e-12, ik
+            assert abs(exv[ik] - Eref) < 1e-12 * abs(Eref), (exv[ik], Eref)
+        else:
+            assert rel_fro(out[ik], W[ik]) < 1e-6, ik
+            assert abs(exv[ik] - Eref) / atoms < 1e-6, (exv[ik], Eref)
 
 
 # uneven Gamma systems: (grid, h, omega, bands, occupied, seed); the first two
@@ -129,13 +131,31 @@ def _gamma_tasks(kx, prec, systems):
     return plans, tasks
 
 
+def _oracle_systems(prec, systems):
+    """Vx and E_x of each system from the FP64 oracle, on the inputs as the
+    device holds them (rounded to FP32 for the mixed-precision plans)."""
+    out = []
+    for n, h, omega, nb, no, seed in systems:
+        psi = random_orbitals(n, (h,) * 3, nb, seed=seed)
+        if prec != "fp64":
+            psi = psi.astype(np.float32).astype(np.float64)
+        g = fermi_occupations(nb, no, 0.01, seed=seed)
+        S = KronSolver(n, (h,) * 3, BCP, 12, omega)
+        W = vx_apply(psi[:no], g[:no], psi, S)
+        out.append((W, exchange_energy(psi, g, W, S.dV), 2.0 * g.sum() / 14.0))
+    return out
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 def test_uneven_systems_ragged_batches(kx, prec, monkeypatch):
     # a small workspace cuts every task into several batches of uneven size,
-    # so rounds hold batches of different systems and ragged last batches
+    # so rounds hold batches of different systems and ragged last batches;
+    # every replay against the FP64 oracle (FP64 1e-12, mixed 1e-6 on Vx and
+    # 1e-6 Ha per nominal atom on E_x) and against per-task exx_apply calls
     say("batched uneven systems", prec)
     monkeypatch.setenv("KX_WORKSPACE_MB", "1")
     plans, tasks = _gamma_tasks(kx, prec, SYSTEMS)
+    ora = _oracle_systems(prec, SYSTEMS)
     try:
         ref = [_eager(kx, t) for t in tasks]
         for rep in range(2):
@@ -145,9 +165,15 @@ def test_uneven_systems_ragged_batches(kx, prec, monkeypatch):
             kx.exx_apply_batched(tasks)
             torch.cuda.synchronize()
             tol = 1e-14 if prec == "fp64" else 1e-6
-            for i, (t, (vx_e, ex_e)) in enumerate(zip(tasks, ref)):
+            for i, (t, (vx_e, ex_e), (W, E, atoms)) in enumerate(zip(tasks, ref, ora)):
                 assert _rel(t["vx"], vx_e) < tol, (rep, i, _rel(t["vx"], vx_e))
                 assert abs(float(t["ex"][0] - ex_e[0])) <= tol * abs(float(ex_e[0])), (rep, i)
+                err = rel_fro(to_host(t["vx"]), W)
+                dE = abs(float(t["ex"][0]) - E)
+                if prec == "fp64":
+                    assert err < 1e-12 and dE < 1e-12 * abs(E), (rep, i, err, dE)
+                else:
+                    assert err < 1e-6 and dE / atoms < 1e-6, (rep, i, err, dE / atoms)
         rounds, batches, launches, widest = kx.kx_batched_schedule()
         assert batches > len(SYSTEMS) and rounds >= 2
         assert widest >= 2 and launches < 3 * batches, (rounds, batches, launches, widest)

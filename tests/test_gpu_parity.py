@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle.exx import exchange_energy, vx_apply
+from oracle.exx import exchange_energy, vx_apply, vx_apply_kpoints
 from oracle.kron import KronSolver
 from paper_2501_16572_amd.workloads import CONFIGS, fermi_occupations, make_inputs, random_orbitals
 
@@ -385,15 +385,18 @@ def test_kron_solve_bloch(kx, case, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_exx_kpoints(kx, prec):
-    # Two k-points; Vx psi_k = sum_q exx_apply(plan(k - q), psi_q, w_q g_q, psi_k)
+    # Two k-points with unequal weights and different occupations (and
+    # occupied counts) at each; Vx psi_k = sum_q exx_apply(plan(k - q),
+    # psi_q, w_q g_q, psi_k), against the oracle's k-point sum.
     n, h = (16, 18, 14), (0.35, 0.35, 0.35)
     say("exx k-points", prec)
     L = [n[d] * h[d] for d in range(3)]
     kpts = [(2 * np.pi / L[0] * 0.25, 2 * np.pi / L[1] * 0.25, 0.0),
             (-2 * np.pi / L[0] * 0.25, 2 * np.pi / L[1] * 0.25, 0.0)]
-    wk = [0.5, 0.5]
+    wk = [0.625, 0.375]
     psi = [random_orbitals(n, h, 5, seed=60 + i, kpt=k, decay=2.0) for i, k in enumerate(kpts)]
-    g = [np.array([1.0, 1.0, 0.7, 0.0, 0.0])] * 2
+    g = [np.array([1.0, 0.95, 0.7, 0.0, 0.0]), np.array([1.0, 0.55, 0.0, 0.0, 0.0])]
+    nocc = [3, 2]
     ct = torch.complex128 if prec == "fp64" else torch.complex64
     if prec == "fp32":
         psi = [p.astype(np.complex64).astype(np.complex128) for p in psi]
@@ -408,31 +411,26 @@ def test_exx_kpoints(kx, prec):
             for iq in range(2):
                 kq = tuple(kpts[ik][d] - kpts[iq][d] for d in range(3))
                 plans[(ik, iq)] = kx.kron_setup(n, h, BCP, 12, 0.0, kq=kq, prec=prec, complex=True)
-                occ = to_dev(wk[iq] * g[iq][:3], torch.float64)
-                kx.exx_apply(plans[(ik, iq)], dev_psi[iq][:3], occ, dev_psi[ik], vx, ex=e, gphi=gphi)
+                occ = to_dev(wk[iq] * g[iq][:nocc[iq]], torch.float64)
+                kx.exx_apply(plans[(ik, iq)], dev_psi[iq][:nocc[iq]], occ, dev_psi[ik], vx, ex=e, gphi=gphi)
             torch.cuda.synchronize()
             out.append(to_host(vx))
             ex.append(float(to_host(e)[0]))
     finally:
         for p in plans.values():
             p.destroy()
-
-    def solver_for(ik, iq):
-        kq = tuple(kpts[ik][d] - kpts[iq][d] for d in range(3))
-        return KronSolver(n, h, BCP, 12, 0.0, kq)
-
-    W = vx_apply_kpoints_ref(psi, g, wk, solver_for)
-    tol = 1e-12 if prec == "fp64" else 1e-6
+    W = vx_apply_kpoints(psi, g, wk, kpts, lambda kq: KronSolver(n, h, BCP, 12, 0.0, kq))
+    dV = float(np.prod(h))
+    atoms = 2.0 * sum(wk[i] * g[i].sum() for i in range(2)) / 14.0
     for ik in range(2):
-        assert rel_fro(out[ik], W[ik]) < tol, ik
-        Eref = wk[ik] * float(np.sum(g[ik] * np.real(np.sum(np.conj(psi[ik]) * W[ik], axis=1)))) * np.prod(h)
-        assert abs(ex[ik] - Eref) < tol * abs(Eref) * 10, (ex[ik], Eref)
+        Eref = wk[ik] * exchange_energy(psi[ik], g[ik], W[ik], dV)
+        if prec == "fp64":
+            assert rel_fro(out[ik], W[ik]) < 1e-12, ik
+            assert abs(ex[ik] - Eref) < 1e-12 * abs(Eref), (ex[ik], Eref)
+        else:
+            assert rel_fro(out[ik], W[ik]) < 1e-6, ik
+            assert abs(ex[ik] - Eref) / atoms < 1e-6, (ex[ik], Eref)
     assert sum(ex) < 0
-
-
-def vx_apply_kpoints_ref(psi, g, wk, solver_for):
-    from oracle.exx import vx_apply_kpoints
-    return vx_apply_kpoints(psi, g, wk, solver_for)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
