@@ -192,6 +192,15 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream);
  * *bytes = 0 when n_b or n_occ is 0. */
 kx_status kx_workspace_bytes(kx_plan p, int n_b, int n_occ, int64_t* bytes);
 
+/* kx_graph_cache_info -- state of exx_apply_batched's cache of captured
+ * graphs: out[0] = task lists held now, out[1] = the most it holds (8; a new
+ * capture beyond that drops the least recently replayed list and frees its
+ * graph and device task tables), out[2] = captures so far in this process.
+ * A cached list is replayed only when every field of every task matches and
+ * no plan of it has reallocated a buffer or been retuned (kx_autotune) since
+ * the capture; otherwise it is captured again.  Host only. */
+kx_status kx_graph_cache_info(int64_t out[3]);
+
 /* kx_batched_schedule -- shape of the schedule that the last capture of
  * exx_apply_batched in this process built: out[0] = rounds, out[1] = batches
  * (one task contributes ceil(n_b / targets per batch)), out[2] = launches of

@@ -151,11 +151,12 @@ hipError_t traced(int kind, hipStream_t s, F fn) {
 
 struct kx_graph_entry {
   std::vector<kx_task> tasks;
-  std::vector<unsigned> generations;  // workspace generation of each task's plan at capture
+  std::vector<unsigned> generations;  // generation of each task's plan at capture
   hipStream_t stream;
   hipGraph_t graph;
   hipGraphExec_t exec;
   void* d_tables;                     // task tables of the grouped launches (device)
+  uint64_t last_use;                  // replay clock of the last capture or replay
 };
 
 void destroy_graph_entry(kx_graph_entry& g) {
@@ -195,7 +196,10 @@ struct kx_plan_s {
   size_t part_bytes = 0;
   int last_nt = 0;
   int max_blocks = 0;    // 0: as many as are co-resident
-  unsigned ws_gen = 0;   // bumped whenever a device buffer is reallocated
+  // Bumped whenever a device buffer is reallocated or the launch
+  // configuration changes (kx_autotune): graphs captured at an older
+  // generation hold stale pointers or configurations and are captured again.
+  unsigned gen = 0;
   // launch configuration per fused pass (A, B, C): occupancy variant and
   // resident blocks per CU (0 = all that fit); set by kx_autotune
   int tune_tv[3] = {0, 0, 0};
@@ -207,6 +211,17 @@ namespace {
 
 std::mutex g_graph_mu;
 std::vector<kx_graph_entry> g_graphs;
+// At most this many captured task lists are kept; the least recently
+// replayed one is dropped to make room for a new capture.
+constexpr size_t kGraphCacheCap = 8;
+uint64_t g_graph_clock = 0;
+uint64_t g_graph_captures = 0;
+
+bool same_task(const kx_task& a, const kx_task& b) {
+  return a.plan == b.plan && a.d_psi == b.d_psi && a.ld_psi == b.ld_psi && a.n_occ == b.n_occ &&
+         a.d_occ == b.d_occ && a.d_phi == b.d_phi && a.ld_phi == b.ld_phi && a.n_b == b.n_b &&
+         a.d_vx == b.d_vx && a.ld_vx == b.ld_vx && a.d_ex == b.d_ex && a.d_gphi == b.d_gphi;
+}
 
 size_t workspace_limit() {
   const char* env = std::getenv("KX_WORKSPACE_MB");
@@ -443,7 +458,7 @@ kx_status prepare_exx(kx_plan p, int n_occ, int n_b, int path) {
   const size_t per_t = std::max<size_t>(64, (size_t)p->n[2]);
   st = ensure_buffer((void**)&p->d_part, &p->part_bytes, (size_t)nt * per_t * sizeof(double),
                      "E_x partials");
-  if (p->d_ws != ws0 || p->d_part != part0) ++p->ws_gen;
+  if (p->d_ws != ws0 || p->d_part != part0) ++p->gen;
   return st;
 }
 
@@ -795,7 +810,7 @@ kx_status kron_solve_slicewise(kx_plan p, const double* B, int64_t ldb, double* 
   void* ws0 = p->d_ws;
   kx_status st = ensure_buffer(&p->d_ws, &p->ws_bytes, (size_t)p->N * sizeof(double), "slice-wise workspace");
   if (st != KX_OK) return st;
-  if (p->d_ws != ws0) ++p->ws_gen;  // cached exx graphs must re-capture
+  if (p->d_ws != ws0) ++p->gen;  // cached exx graphs must re-capture
   const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2], n12 = p->n12;
   // dVmat[d] holds V_d[grid k][mode a] at k*P + a, i.e. V_d^T as a
   // column-major matrix; dVmatT[d] is V_d itself, column-major
@@ -1001,6 +1016,7 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
       p->tune_bpc[i] = bpc[i];
     }
     p->tuned = true;
+    ++p->gen;  // graphs captured with the previous configuration are stale
     return KX_OK;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -1069,6 +1085,7 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
     bpc[i] = p->tune_bpc[i];
   }
   p->tuned = true;
+  ++p->gen;
   tune_cache_store(key, tv, bpc);
   return KX_OK;
 }
@@ -1154,19 +1171,30 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
   }
   for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
     kx_graph_entry& g = *it;
-    if (g.stream == s && (int)g.tasks.size() == ntasks &&
-        std::memcmp(g.tasks.data(), tasks, sizeof(kx_task) * ntasks) == 0) {
-      bool fresh = true;
-      for (int i = 0; i < ntasks; ++i) fresh &= g.generations[i] == tasks[i].plan->ws_gen;
-      if (!fresh) {  // a workspace moved since capture: capture again
-        destroy_graph_entry(g);
-        g_graphs.erase(it);
-        break;
-      }
-      hipError_t e = hipGraphLaunch(g.exec, s);
-      if (e != hipSuccess) return dev_fail(e, "exx_apply_batched replay");
-      return KX_OK;
+    if (g.stream != s || (int)g.tasks.size() != ntasks) continue;
+    bool same = true;
+    for (int i = 0; i < ntasks && same; ++i) same = same_task(g.tasks[i], tasks[i]);
+    if (!same) continue;
+    bool fresh = true;
+    for (int i = 0; i < ntasks; ++i) fresh &= g.generations[i] == tasks[i].plan->gen;
+    if (!fresh) {  // a workspace moved or a plan was retuned since capture
+      (void)hipDeviceSynchronize();  // an earlier replay may still read its tables
+      destroy_graph_entry(g);
+      g_graphs.erase(it);
+      break;
     }
+    g.last_use = ++g_graph_clock;
+    hipError_t e = hipGraphLaunch(g.exec, s);
+    if (e != hipSuccess) return dev_fail(e, "exx_apply_batched replay");
+    return KX_OK;
+  }
+  if (g_graphs.size() >= kGraphCacheCap) {
+    auto lru = g_graphs.begin();
+    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+      if (it->last_use < lru->last_use) lru = it;
+    (void)hipDeviceSynchronize();
+    destroy_graph_entry(*lru);
+    g_graphs.erase(lru);
   }
 
   // Schedule: per round, the batches of each pass are grouped by kernel
@@ -1330,8 +1358,10 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
     return dev_fail(e, "exx_apply_batched instantiate");
   }
   std::vector<unsigned> gens(ntasks);
-  for (int i = 0; i < ntasks; ++i) gens[i] = tasks[i].plan->ws_gen;
-  g_graphs.push_back(kx_graph_entry{std::vector<kx_task>(tasks, tasks + ntasks), gens, s, graph, exec, d_tab});
+  for (int i = 0; i < ntasks; ++i) gens[i] = tasks[i].plan->gen;
+  g_graphs.push_back(kx_graph_entry{std::vector<kx_task>(tasks, tasks + ntasks), gens, s, graph, exec, d_tab,
+                                    ++g_graph_clock});
+  ++g_graph_captures;
   e = hipGraphLaunch(exec, s);
   if (e != hipSuccess) return dev_fail(e, "exx_apply_batched launch");
   return KX_OK;
@@ -1439,6 +1469,15 @@ kx_status ace_apply(int64_t N, int n_s, int cplx, double dV, const void* d_xi, i
   if (e == hipSuccess)
     e = kx::launch_ace_tsmm(cplx, N, n_s, n_phi, d_xi, ld_xi, chi, -1.0, 1.0, d_vphi, ld_vphi, nullptr, s);
   if (e != hipSuccess) return dev_fail(e, "ace_apply launch");
+  return KX_OK;
+}
+
+kx_status kx_graph_cache_info(int64_t out[3]) {
+  if (!out) return fail(KX_EINVAL, "kx_graph_cache_info: NULL argument");
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  out[0] = (int64_t)g_graphs.size();
+  out[1] = (int64_t)kGraphCacheCap;
+  out[2] = (int64_t)g_graph_captures;
   return KX_OK;
 }
 

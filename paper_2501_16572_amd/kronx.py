@@ -34,7 +34,7 @@ EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_b
            "kx_plan_info", "kx_plan_tables", "kx_host_eig1d", "kx_host_fd_weights",
            "kx_last_error", "kx_trace_enable", "kx_trace_read", "kx_trace_name", "kx_autotune",
            "kx_plan_tuning", "kx_batched_schedule", "kx_workspace_bytes", "kx_ace_workspace_bytes",
-           "ace_construct", "ace_apply"]
+           "ace_construct", "ace_apply", "kx_graph_cache_info"]
 
 
 class KronxError(RuntimeError):
@@ -84,6 +84,7 @@ def load_library(path=None):
     lib.kx_autotune.argtypes = [vp, vp, i64, ci, vp, vp, i64, ci, vp]
     lib.kx_plan_tuning.argtypes = [vp, ip]
     lib.kx_batched_schedule.argtypes = [ip]
+    lib.kx_graph_cache_info.argtypes = [i64p]
     lib.kx_workspace_bytes.argtypes = [vp, ci, ci, ctypes.POINTER(i64)]
     lib.kx_ace_workspace_bytes.argtypes = [i64, ci, ci, ci, ctypes.POINTER(i64)]
     lib.ace_construct.argtypes = [i64, ci, ci, cd, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp]
@@ -203,6 +204,71 @@ def _cols(t, N, what):
     return t.data_ptr(), ld
 
 
+def _on_device(t, what):
+    if not t.is_cuda:
+        raise ValueError(f"{what}: must be a GPU tensor (got device {t.device})")
+
+
+def _grid_set(t, N, dtype, what, rows=None):
+    """A (ncols, N) set of grid functions of `dtype` on the GPU, with at least
+    `rows` rows when given; returns (pointer, leading dimension)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, the plan needs {dtype}")
+    out = _cols(t, N, what)
+    if rows is not None and t.shape[0] < rows:
+        raise ValueError(f"{what}: {t.shape[0]} rows, at least {rows} needed")
+    return out
+
+
+def _vector(t, n, dtype, what):
+    """A contiguous GPU vector of `dtype` with at least n entries; its pointer."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, {dtype} needed")
+    if not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{what}: a contiguous tensor of at least {n} entries is needed "
+                         f"(got {tuple(t.shape)})")
+    return t.data_ptr()
+
+
+def _all_on_device(**tensors):
+    """After the shape and type checks: every tensor must live on the GPU."""
+    for what, t in tensors.items():
+        if t is not None:
+            _on_device(t, what)
+
+
+def _vx_dtype(plan):
+    import torch
+    return torch.complex128 if plan.complex else torch.float64
+
+
+def _exx_args(plan, psi, occ, phi, vx, ex, gphi):
+    """Pointers and leading dimensions of one exx_apply call, every tensor
+    checked against the plan before the library sees it."""
+    import torch
+    N = plan.N
+    pp, ldp = _grid_set(psi, N, plan.dtype, "psi")
+    pf, ldf = _grid_set(phi, N, plan.dtype, "phi")
+    n_occ, n_b = psi.shape[0], phi.shape[0]
+    pv, ldv = _grid_set(vx, N, _vx_dtype(plan), "vx", rows=n_b)
+    po = _vector(occ, n_occ, torch.float64, "occ")
+    pe = pg = None
+    if ex is not None:
+        pe = _vector(ex, 1, torch.float64, "ex")
+        if gphi is None:
+            raise ValueError("ex given without gphi")
+    if gphi is not None:
+        pg = _vector(gphi, n_b, torch.float64, "gphi")
+    _all_on_device(psi=psi, phi=phi, vx=vx, occ=occ, ex=ex, gphi=gphi)
+    return dict(psi=(pp, ldp, n_occ), phi=(pf, ldf, n_b), vx=(pv, ldv), occ=po, ex=pe, gphi=pg)
+
+
 def kron_solve(plan, B, X=None, path="fused", stream=None):
     """X = f(L) B for the rows of B (shape (nrhs, N)); returns X.
 
@@ -212,8 +278,9 @@ def kron_solve(plan, B, X=None, path="fused", stream=None):
     import torch
     if X is None:
         X = torch.empty_like(B)
-    pb, ldb = _cols(B, plan.N, "B")
-    px, ldx = _cols(X, plan.N, "X")
+    pb, ldb = _grid_set(B, plan.N, plan.dtype, "B")
+    px, ldx = _grid_set(X, plan.N, plan.dtype, "X", rows=B.shape[0])
+    _all_on_device(B=B, X=X)
     st = load_library().kron_solve(plan.handle, ctypes.c_void_p(pb), ldb, ctypes.c_void_p(px), ldx,
                                    B.shape[0], PATH[path], _stream(stream))
     _check(st, "kron_solve")
@@ -225,16 +292,19 @@ def exx_apply(plan, psi, occ, phi, vx, ex=None, gphi=None, path="fused", stream=
 
     psi: (n_occ, N), occ: (n_occ,) float64, phi: (n_b, N), vx: (n_b, N) float64
     (complex128 for complex plans), ex: (1,) float64 or None, gphi: (n_b,) float64.
-    All CUDA tensors.  Returns vx.
+    psi and phi have the plan's element type (plan.dtype).  All GPU tensors;
+    a tensor that does not fit raises ValueError before the library is called.
+    Returns vx.
     """
-    pp, ldp = _cols(psi, plan.N, "psi")
-    pf, ldf = _cols(phi, plan.N, "phi")
-    pv, ldv = _cols(vx, plan.N, "vx")
+    a = _exx_args(plan, psi, occ, phi, vx, ex, gphi)
+    pp, ldp, n_occ = a["psi"]
+    pf, ldf, n_b = a["phi"]
+    pv, ldv = a["vx"]
     st = load_library().exx_apply(
-        plan.handle, ctypes.c_void_p(pp), ldp, psi.shape[0], ctypes.c_void_p(occ.data_ptr()),
-        ctypes.c_void_p(pf), ldf, phi.shape[0], ctypes.c_void_p(pv), ldv,
-        ctypes.c_void_p(ex.data_ptr()) if ex is not None else None,
-        ctypes.c_void_p(gphi.data_ptr()) if gphi is not None else None,
+        plan.handle, ctypes.c_void_p(pp), ldp, n_occ, ctypes.c_void_p(a["occ"]),
+        ctypes.c_void_p(pf), ldf, n_b, ctypes.c_void_p(pv), ldv,
+        ctypes.c_void_p(a["ex"]) if a["ex"] is not None else None,
+        ctypes.c_void_p(a["gphi"]) if a["gphi"] is not None else None,
         PATH[path], _stream(stream))
     _check(st, "exx_apply")
     return vx
@@ -242,27 +312,29 @@ def exx_apply(plan, psi, occ, phi, vx, ex=None, gphi=None, path="fused", stream=
 
 def kx_autotune(plan, psi, occ, phi, stream=None):
     """Pick the fused passes' launch configuration on this workload (synchronous)."""
-    pp, ldp = _cols(psi, plan.N, "psi")
-    pf, ldf = _cols(phi, plan.N, "phi")
+    import torch
+    pp, ldp = _grid_set(psi, plan.N, plan.dtype, "psi")
+    pf, ldf = _grid_set(phi, plan.N, plan.dtype, "phi")
+    po = _vector(occ, psi.shape[0], torch.float64, "occ")
+    _all_on_device(psi=psi, phi=phi, occ=occ)
     st = load_library().kx_autotune(plan.handle, ctypes.c_void_p(pp), ldp, psi.shape[0],
-                                    ctypes.c_void_p(occ.data_ptr()), ctypes.c_void_p(pf), ldf,
+                                    ctypes.c_void_p(po), ctypes.c_void_p(pf), ldf,
                                     phi.shape[0], _stream(stream))
     _check(st, "kx_autotune")
     return plan.tuning()
 
 
 def exx_apply_batched(tasks, stream=None):
-    """tasks: list of dicts with keys plan, psi, occ, phi, vx, ex (opt), gphi (opt)."""
+    """tasks: list of dicts with keys plan, psi, occ, phi, vx, ex (opt), gphi (opt),
+    each checked as exx_apply checks its arguments."""
     arr = (_Task * len(tasks))()
     for i, t in enumerate(tasks):
         plan = t["plan"]
-        pp, ldp = _cols(t["psi"], plan.N, "psi")
-        pf, ldf = _cols(t["phi"], plan.N, "phi")
-        pv, ldv = _cols(t["vx"], plan.N, "vx")
-        ex, gphi = t.get("ex"), t.get("gphi")
-        arr[i] = _Task(plan.handle.value, pp, ldp, t["psi"].shape[0], t["occ"].data_ptr(), pf, ldf,
-                       t["phi"].shape[0], pv, ldv, ex.data_ptr() if ex is not None else None,
-                       gphi.data_ptr() if gphi is not None else None)
+        a = _exx_args(plan, t["psi"], t["occ"], t["phi"], t["vx"], t.get("ex"), t.get("gphi"))
+        pp, ldp, n_occ = a["psi"]
+        pf, ldf, n_b = a["phi"]
+        pv, ldv = a["vx"]
+        arr[i] = _Task(plan.handle.value, pp, ldp, n_occ, a["occ"], pf, ldf, n_b, pv, ldv, a["ex"], a["gphi"])
     _check(load_library().exx_apply_batched(arr, len(tasks), _stream(stream)), "exx_apply_batched")
 
 
@@ -284,23 +356,36 @@ def kx_ace_workspace_bytes(N, n_s, n_phi, cplx):
 def _ace_work(N, n_s, n_phi, cplx, work):
     import torch
     need = kx_ace_workspace_bytes(N, n_s, n_phi, cplx)
-    if work is None or work.numel() * work.element_size() < need:
-        work = torch.empty(need // 8 + 64, dtype=torch.float64, device="cuda")
+    if work is None:
+        return torch.empty(need // 8 + 64, dtype=torch.float64, device="cuda")
+    if not isinstance(work, torch.Tensor) or not work.is_contiguous():
+        raise ValueError("work: expected a contiguous torch tensor")
+    if work.numel() * work.element_size() < need:
+        raise ValueError(f"work: {work.numel() * work.element_size()} bytes, {need} needed")
     return work
+
+
+def _ace_dtype(t, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype not in (torch.float64, torch.complex128):
+        raise ValueError(f"{what}: expected a float64 or complex128 torch tensor")
+    return t.dtype
 
 
 def ace_construct(psi, w, dV, xi=None, work=None, stream=None):
     """xi (n_s, N) of the ACE operator from psi and w = Vx psi (both (n_s, N),
-    float64 or complex128, CUDA).  Raises if -dV psi^H w is not positive definite."""
+    float64 or complex128, GPU).  Raises if -dV psi^H w is not positive definite."""
     import torch
+    dt = _ace_dtype(psi, "psi")
     n_s, N = psi.shape
     cplx = psi.is_complex()
     if xi is None:
         xi = torch.empty_like(w)
-    pp, ldp = _cols(psi, N, "psi")
-    pw, ldw = _cols(w, N, "w")
-    px, ldx = _cols(xi, N, "xi")
+    pp, ldp = _grid_set(psi, N, dt, "psi")
+    pw, ldw = _grid_set(w, N, dt, "w", rows=n_s)
+    px, ldx = _grid_set(xi, N, dt, "xi", rows=n_s)
     work = _ace_work(N, n_s, 0, cplx, work)
+    _all_on_device(psi=psi, w=w, xi=xi, work=work)
     info = torch.zeros(1, dtype=torch.int32, device=psi.device)
     st = load_library().ace_construct(N, n_s, 1 if cplx else 0, float(dV), ctypes.c_void_p(pp), ldp,
                                       ctypes.c_void_p(pw), ldw, ctypes.c_void_p(px), ldx,
@@ -314,13 +399,15 @@ def ace_construct(psi, w, dV, xi=None, work=None, stream=None):
 
 
 def ace_apply(xi, phi, dV, vphi, work=None, stream=None):
-    """vphi += -xi (dV xi^H phi); xi (n_s, N), phi and vphi (n_phi, N)."""
+    """vphi += -xi (dV xi^H phi); xi (n_s, N), phi and vphi (n_phi, N), one dtype."""
+    dt = _ace_dtype(xi, "xi")
     n_s, N = xi.shape
     cplx = xi.is_complex()
-    px, ldx = _cols(xi, N, "xi")
-    pf, ldf = _cols(phi, N, "phi")
-    pv, ldv = _cols(vphi, N, "vphi")
+    px, ldx = _grid_set(xi, N, dt, "xi")
+    pf, ldf = _grid_set(phi, N, dt, "phi")
+    pv, ldv = _grid_set(vphi, N, dt, "vphi", rows=phi.shape[0])
     work = _ace_work(N, n_s, phi.shape[0], cplx, work)
+    _all_on_device(xi=xi, phi=phi, vphi=vphi, work=work)
     st = load_library().ace_apply(N, n_s, 1 if cplx else 0, float(dV), ctypes.c_void_p(px), ldx,
                                   ctypes.c_void_p(pf), ldf, phi.shape[0], ctypes.c_void_p(pv), ldv,
                                   ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size(),
@@ -334,6 +421,13 @@ def kx_batched_schedule():
     (rounds, batches, launches of the three passes, most batches in one launch)."""
     out = (ctypes.c_int * 4)()
     _check(load_library().kx_batched_schedule(out), "kx_batched_schedule")
+    return tuple(out)
+
+
+def kx_graph_cache_info():
+    """(task lists cached now, cache capacity, captures so far) of exx_apply_batched."""
+    out = (ctypes.c_int64 * 3)()
+    _check(load_library().kx_graph_cache_info(out), "kx_graph_cache_info")
     return tuple(out)
 
 

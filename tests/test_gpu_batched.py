@@ -245,3 +245,48 @@ def test_workspace_bytes_and_balanced_batches(kx, monkeypatch):
         assert rel_fro(to_host(vx), vx_apply(psi[:no], g[:no], psi, S)) < 1e-12
     finally:
         plan.destroy()
+
+
+def test_graph_cache_bounded_and_retuned(kx, tmp_path, monkeypatch):
+    # fresh output tensors on every call make every task list new: the cache
+    # stays at its capacity, and every call still matches the eager result;
+    # an unchanged list replays without a capture, and retuning the plan makes
+    # the next call capture again
+    say("graph cache")
+    monkeypatch.setenv("KX_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    n, h, nb, no = (24, 24, 24), (0.3,) * 3, 3, 2
+    psi = random_orbitals(n, h, nb, seed=98)
+    g = fermi_occupations(nb, no, 0.01, seed=98)
+    plan = kx.kron_setup(n, h, BCP, 12, 0.106, prec="fp64")
+    try:
+        psid = to_dev(psi, torch.float64)
+        occ = to_dev(g[:no], torch.float64)
+        vx_e = torch.zeros_like(psid)
+        kx.exx_apply(plan, psid[:no], occ, psid, vx_e)
+        torch.cuda.synchronize()
+        held, cap, cap0 = kx.kx_graph_cache_info()
+        outs = []
+        for i in range(cap + 4):
+            vx = torch.zeros_like(psid)
+            outs.append(vx)
+            kx.exx_apply_batched([dict(plan=plan, psi=psid[:no], occ=occ, phi=psid, vx=vx)])
+            torch.cuda.synchronize()
+            assert torch.equal(vx, vx_e), i
+            held, cap_i, caps = kx.kx_graph_cache_info()
+            assert cap_i == cap and held <= cap, (held, cap)
+            assert caps == cap0 + i + 1
+        assert held == cap
+        task = [dict(plan=plan, psi=psid[:no], occ=occ, phi=psid, vx=outs[-1])]
+        outs[-1].zero_()
+        kx.exx_apply_batched(task)
+        torch.cuda.synchronize()
+        assert kx.kx_graph_cache_info()[2] == caps          # replayed
+        assert torch.equal(outs[-1], vx_e)
+        kx.kx_autotune(plan, psid[:no], occ, psid)
+        outs[-1].zero_()
+        kx.exx_apply_batched(task)
+        torch.cuda.synchronize()
+        assert kx.kx_graph_cache_info()[2] == caps + 1      # captured again
+        assert rel_fro(to_host(outs[-1]), to_host(vx_e)) < 1e-13
+    finally:
+        plan.destroy()
