@@ -161,3 +161,37 @@ def test_matrix_product_counts_stated_in_paper():
     for nc, val in zip(gold["batch_gemms_per_system"]["n_c"],
                        gold["batch_gemms_per_system"]["value"]):
         assert KronSolver.gemm_count_batch(nc) == pytest.approx(val)
+
+
+def _symbol_longdouble(n, h, order, kappa):
+    """Spectrum of the periodic / Bloch FD operator from the circulant
+    closed form, -4/h^2 sum_s c_s sin^2(s theta_q / 2) with
+    theta_q = 2 pi q / n + kappa h, in extended precision (the exact rational
+    weights rounded once to long double)."""
+    ld = np.longdouble
+    c = fd_weights(order)
+    th = ld(2) * ld(np.pi) * np.arange(n, dtype=ld) / ld(n) + ld(kappa) * ld(h)
+    acc = np.zeros(n, dtype=ld)
+    for s in range(1, len(c)):
+        cs = ld(c[s].numerator) / ld(c[s].denominator)
+        acc += cs * np.sin(ld(s) * th / ld(2)) ** 2
+    return np.sort((ld(-4) * acc / (ld(h) * ld(h))).astype(np.float64))
+
+
+@pytest.mark.parametrize("n,h,kappa", [(80, 0.25, np.pi / 20.0), (80, 0.25, 0.3), (80, 0.25, 0.0),
+                                       (120, 0.2, 0.0), (7, 0.3, 0.6), (160, 0.3125, 0.01)])
+def test_periodic_eigenvalues_relative_accuracy(n, h, kappa):
+    # Every eigenvalue of the periodic / Bloch axis, the smallest included,
+    # well inside the FP64 parity bar (1e-12) in relative terms, against the
+    # closed form in extended precision: the unscreened kernel -4 pi / lambda
+    # carries the relative error of the smallest |lambda| straight into the
+    # dominant modes of the solution.  (A Hermitian eigensolver's own
+    # eigenvalues miss this by up to 3e-11 on these axes; the Rayleigh
+    # quotient's error grows only like eps / theta for the mode at angle theta.)
+    S = KronSolver((n, 4, 4), (h, 0.3, 0.3), ("periodic",) * 3, 12, 0.0, kappa=(kappa, 0.0, 0.0))
+    lam = np.sort(S.lam[0])
+    ref = _symbol_longdouble(n, h, 12, kappa)
+    scale = np.maximum(np.abs(ref), 1e-300)
+    nonzero = np.abs(ref) > 1e-12 * np.abs(ref).max()
+    assert np.max(np.abs(lam - ref)[nonzero] / scale[nonzero]) < 2e-13
+    assert np.max(np.abs(lam - ref)) < 1e-14 * np.abs(ref).max()
