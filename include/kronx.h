@@ -150,6 +150,28 @@ kx_status exx_apply(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, con
                     const void* d_phi, int64_t ld_phi, int n_b, double* d_vx, int64_t ld_vx,
                     double* d_ex, const double* d_gphi, int path, void* stream);
 
+/* exx_apply_static -- exx_apply that allocates nothing, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Arguments, results, layout and
+ * errors as exx_apply; the plan's device must be the current device.
+ * The pair workspace and the E_x partials live in a fixed device array of
+ * kx_static_scratch_bytes() bytes (256 MiB) inside the library: one copy per
+ * GPU, held until the process ends, shared by every call on that GPU and
+ * keeping the last call's contents (nothing in it needs clearing: each call
+ * writes what it reads).  Calls that overlap in time on one GPU (other
+ * streams, other threads) race on it: serialize them.  A call whose single
+ * target needs more than the array holds, i.e.
+ *   max(64, n3) * 8 * n_b (rounded up to 256) + n_occ * N * element bytes
+ * above 256 MiB, returns KX_EINVAL before any work.  No hipMalloc, hipFree,
+ * memset or trace event. */
+kx_status exx_apply_static(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ,
+                           const double* d_occ, const void* d_phi, int64_t ld_phi, int n_b,
+                           double* d_vx, int64_t ld_vx, double* d_ex, const double* d_gphi,
+                           int path, void* stream);
+
+/* kx_static_scratch_bytes -- size of exx_apply_static's device array. */
+size_t kx_static_scratch_bytes(void);
+
 /* One unit of a batched call: an exx_apply with its own plan.  Field
  * meanings are those of exx_apply's arguments. */
 typedef struct {

@@ -393,7 +393,9 @@ struct BatchArgs {
 };
 BatchArgs batch_args(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, const double* occ,
                      const void* phi, int64_t ld_phi, double* vx, int64_t ld_vx, bool want_ex, int n0,
-                     int cur) {
+                     int cur, void* ws = nullptr, double* part = nullptr) {
+  if (!ws) ws = p->d_ws;
+  if (!part) part = p->d_part;
   const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);  // bytes per grid value
   const size_t vxw = p->cplx ? 2 : 1;                          // doubles per Vx value
   const int npairs = cur * n_occ;
@@ -403,22 +405,22 @@ BatchArgs batch_args(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, cons
   A.n1 = p->n[0]; A.n2 = p->n[1]; A.n3 = p->n[2]; A.n12 = p->n12; A.N = p->N;
   A.npairs = npairs; A.n_occ = n_occ;
   A.psi = psi; A.ld_psi = ld_psi; A.phi = phi0; A.ld_phi = ld_phi;
-  A.src = p->d_ws; A.ld_src = p->N;
-  A.dst = p->d_ws; A.ld_dst = p->N;
+  A.src = ws; A.ld_src = p->N;
+  A.dst = ws; A.ld_dst = p->N;
   A.V1 = p->dVmat[0]; A.V2 = p->dVmat[1]; A.P = p->P12;
   kx::PencilArgs& B = b.B;
   B.n1 = p->n[0]; B.n2 = p->n[1]; B.n3 = p->n[2]; B.n12 = p->n12;
   B.npairs = npairs; B.nchunks = (p->n12 + 63) / 64;
-  B.T = p->d_ws; B.ld = p->N; B.V3 = p->dVmat[2]; B.V3T = p->dVmatT[2]; B.P3 = p->P3; B.ftab = p->d_f;
+  B.T = ws; B.ld = p->N; B.V3 = p->dVmat[2]; B.V3T = p->dVmatT[2]; B.P3 = p->P3; B.ftab = p->d_f;
   kx::AccArgs& C = b.C;
   C.n1 = p->n[0]; C.n2 = p->n[1]; C.n3 = p->n[2]; C.n12 = p->n12; C.N = p->N;
   C.n_t = cur; C.n_occ = n_occ;
-  C.T = p->d_ws; C.ld_T = p->N;
+  C.T = ws; C.ld_T = p->N;
   C.psi = psi; C.ld_psi = ld_psi; C.occ = occ;
   C.phi = phi0; C.ld_phi = ld_phi;
   C.vx = vx + (size_t)n0 * ld_vx * vxw; C.ld_vx = ld_vx;
-  C.partials = want_ex ? p->d_part : nullptr;
-  C.dst = p->d_ws; C.ld_dst = p->N;
+  C.partials = want_ex ? part : nullptr;
+  C.dst = ws; C.ld_dst = p->N;
   C.V1 = p->dVmatT[0]; C.V2 = p->dVmatT[1]; C.P = p->P12;
   return b;
 }
@@ -462,18 +464,30 @@ kx_status prepare_exx(kx_plan p, int n_occ, int n_b, int path) {
   return st;
 }
 
+// ws / part / nt: the pair workspace, the E_x partials and the targets per
+// batch they hold; null / 0 selects the plan-owned buffers.  With
+// untraced, no trace events are created (the allocation-free entry point).
 kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, const double* occ,
                       const void* phi, int64_t ld_phi, int n_b, double* vx, int64_t ld_vx,
-                      double* ex, const double* gphi, int path, hipStream_t s) {
+                      double* ex, const double* gphi, int path, hipStream_t s, void* ws = nullptr,
+                      double* part = nullptr, int nt = 0, bool untraced = false) {
   using namespace kx;
   if (n_occ == 0 || n_b == 0) return KX_OK;
-  const int nt = held_batch(p, n_occ, n_b);
-  if (nt < 1) return fail(KX_ESTATE, "exx_apply: workspace not prepared");
-  p->last_nt = nt;
+  if (nt == 0) {
+    nt = held_batch(p, n_occ, n_b);
+    if (nt < 1) return fail(KX_ESTATE, "exx_apply: workspace not prepared");
+    p->last_nt = nt;
+  }
+  if (!ws) ws = p->d_ws;
+  if (!part) part = p->d_part;
+  auto traced = [untraced](int kind, hipStream_t st, auto fn) -> hipError_t {
+    return untraced ? fn() : ::traced(kind, st, fn);
+  };
   for (int n0 = 0; n0 < n_b; n0 += nt) {
     const int cur = std::min(nt, n_b - n0);
     const int npairs = cur * n_occ;
-    const BatchArgs ba = batch_args(p, psi, ld_psi, n_occ, occ, phi, ld_phi, vx, ld_vx, ex != nullptr, n0, cur);
+    const BatchArgs ba = batch_args(p, psi, ld_psi, n_occ, occ, phi, ld_phi, vx, ld_vx, ex != nullptr, n0, cur,
+                                    ws, part);
     const kx::SliceArgs& A = ba.A;
     const kx::PencilArgs& B = ba.B;
     const kx::AccArgs& C = ba.C;
@@ -495,7 +509,7 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
         e = traced(TK_P_M2F, s, [&] { return launch_slice_fwd_f64(p->nk12, SF_LOAD2, A, items_pairs, mb, s); });
       if (e == hipSuccess) e = traced(TK_P_M3F, s, [&] { return launch_pencil_f64(p->nk3, PC_F, B, mb, s); });
       if (e == hipSuccess)
-        e = traced(TK_P_SCALE, s, [&] { return launch_scale_f64((double*)p->d_ws, p->N, npairs, p->N, p->d_f, s); });
+        e = traced(TK_P_SCALE, s, [&] { return launch_scale_f64((double*)ws, p->N, npairs, p->N, p->d_f, s); });
       if (e == hipSuccess) e = traced(TK_P_M3I, s, [&] { return launch_pencil_f64(p->nk3, PC_I, B, mb, s); });
       AccArgs Cs = C;
       Cs.n_t = npairs; Cs.n_occ = 1;
@@ -507,7 +521,7 @@ kx_status enqueue_exx(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, con
       if (e == hipSuccess) e = traced(TK_P_ACC, s, [&] { return launch_accumulate_f64(C, per_target, s); });
     }
     if (e == hipSuccess && ex)
-      e = traced(TK_FIN, s, [&] { return launch_ex_finalize(p->d_part, cur, per_target, gphi + n0, p->dV, ex, s); });
+      e = traced(TK_FIN, s, [&] { return launch_ex_finalize(part, cur, per_target, gphi + n0, p->dV, ex, s); });
     if (e != hipSuccess) return dev_fail(e, "exx_apply launch");
   }
   return KX_OK;
@@ -914,6 +928,80 @@ kx_status exx_apply(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, con
   if (st != KX_OK) return st;
   return enqueue_exx(p, d_psi, ld_psi, n_occ, d_occ, d_phi, ld_phi, n_b, d_vx, ld_vx, d_ex, d_gphi,
                      path, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// exx_apply_static: exx_apply without any device allocation.  The pair
+// workspace and the E_x partials live in `scratch`, a fixed device array of
+// this translation unit (one copy per GPU, held until the process ends).  In
+// host code `scratch` names a host-side stand-in; its device address on each
+// GPU comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address reaches kernels.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kStaticScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // device address of `scratch`, per device
+
+kx_status static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_fail(e, "exx_apply_static: hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(KX_EDEVICE, "exx_apply_static: hipGetSymbolAddress(scratch) failed: %s",
+                  hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return KX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kx_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+kx_status exx_apply_static(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, const double* d_occ,
+                           const void* d_phi, int64_t ld_phi, int n_b, double* d_vx, int64_t ld_vx,
+                           double* d_ex, const double* d_gphi, int path, void* stream) {
+  kx_status st = check_exx_args(p, d_psi, ld_psi, n_occ, d_occ, d_phi, ld_phi, n_b, d_vx, ld_vx,
+                                d_ex, d_gphi, path);
+  if (st != KX_OK || n_occ == 0 || n_b == 0) return st;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(KX_EINVAL, "exx_apply_static: the plan's device (%d) is not the current device (%d)",
+                p->device, dev);
+  // layout: E_x partials of every target (max(64, n3) doubles each, 256-byte
+  // aligned), then the pair workspace of one batch
+  const size_t per_t_part = std::max<size_t>(64, (size_t)p->n[2]) * sizeof(double);
+  const size_t part_bytes = ((size_t)n_b * per_t_part + 255) / 256 * 256;
+  const size_t per_t_ws = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+  if (part_bytes + per_t_ws > kStaticScratchBytes)
+    return fail(KX_EINVAL,
+                "exx_apply_static: one target needs %zu bytes of scratch (%d occupied x N = %lld), "
+                "more than its fixed %zu bytes; use exx_apply",
+                part_bytes + per_t_ws, n_occ, (long long)p->N, kStaticScratchBytes);
+  const int nt = balanced_batch(n_b, (kStaticScratchBytes - part_bytes) / per_t_ws);
+  void* base = nullptr;
+  st = static_scratch(&base);
+  if (st != KX_OK) return st;
+  double* part = (double*)base;
+  void* ws = (char*)base + part_bytes;
+  return enqueue_exx(p, d_psi, ld_psi, n_occ, d_occ, d_phi, ld_phi, n_b, d_vx, ld_vx, d_ex, d_gphi, path,
+                     (hipStream_t)stream, ws, part, nt, true);
 }
 
 // ---------------------------------------------------------------------------

@@ -34,7 +34,8 @@ EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_b
            "kx_plan_info", "kx_plan_tables", "kx_host_eig1d", "kx_host_fd_weights",
            "kx_last_error", "kx_trace_enable", "kx_trace_read", "kx_trace_name", "kx_autotune",
            "kx_plan_tuning", "kx_batched_schedule", "kx_workspace_bytes", "kx_ace_workspace_bytes",
-           "ace_construct", "ace_apply", "kx_graph_cache_info"]
+           "ace_construct", "ace_apply", "kx_graph_cache_info", "exx_apply_static",
+           "kx_static_scratch_bytes"]
 
 
 class KronxError(RuntimeError):
@@ -71,6 +72,8 @@ def load_library(path=None):
     lib.kron_destroy.argtypes = [vp]
     lib.kron_solve.argtypes = [vp, vp, i64, vp, i64, ci, ci, vp]
     lib.exx_apply.argtypes = [vp, vp, i64, ci, vp, vp, i64, ci, vp, i64, vp, vp, ci, vp]
+    lib.exx_apply_static.argtypes = [vp, vp, i64, ci, vp, vp, i64, ci, vp, i64, vp, vp, ci, vp]
+    lib.kx_static_scratch_bytes.argtypes = []
     lib.exx_apply_batched.argtypes = [ctypes.POINTER(_Task), ci, vp]
     lib.kx_plan_info.argtypes = [vp, i64p]
     lib.kx_plan_tables.argtypes = [vp, ci, dp, dp, dp]
@@ -90,8 +93,9 @@ def load_library(path=None):
     lib.ace_construct.argtypes = [i64, ci, ci, cd, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp]
     lib.ace_apply.argtypes = [i64, ci, ci, cd, vp, i64, vp, i64, ci, vp, i64, vp, i64, vp]
     for name in EXPORTS:
-        if name not in ("kx_last_error", "kx_trace_name"):
+        if name not in ("kx_last_error", "kx_trace_name", "kx_static_scratch_bytes"):
             getattr(lib, name).restype = ci
+    lib.kx_static_scratch_bytes.restype = ctypes.c_size_t
     _lib = lib
     return lib
 
@@ -308,6 +312,28 @@ def exx_apply(plan, psi, occ, phi, vx, ex=None, gphi=None, path="fused", stream=
         PATH[path], _stream(stream))
     _check(st, "exx_apply")
     return vx
+
+
+def exx_apply_static(plan, psi, occ, phi, vx, ex=None, gphi=None, path="fused", stream=None):
+    """exx_apply without any device allocation: the library's fixed device
+    array (kx_static_scratch_bytes()) holds the pair workspace.  Same
+    arguments and result as exx_apply; calls that overlap on one GPU race."""
+    a = _exx_args(plan, psi, occ, phi, vx, ex, gphi)
+    pp, ldp, n_occ = a["psi"]
+    pf, ldf, n_b = a["phi"]
+    pv, ldv = a["vx"]
+    st = load_library().exx_apply_static(
+        plan.handle, ctypes.c_void_p(pp), ldp, n_occ, ctypes.c_void_p(a["occ"]),
+        ctypes.c_void_p(pf), ldf, n_b, ctypes.c_void_p(pv), ldv,
+        ctypes.c_void_p(a["ex"]) if a["ex"] is not None else None,
+        ctypes.c_void_p(a["gphi"]) if a["gphi"] is not None else None,
+        PATH[path], _stream(stream))
+    _check(st, "exx_apply_static")
+    return vx
+
+
+def kx_static_scratch_bytes():
+    return int(load_library().kx_static_scratch_bytes())
 
 
 def kx_autotune(plan, psi, occ, phi, stream=None):

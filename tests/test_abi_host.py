@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     txt = open(os.path.join(ROOT, "include", "kronx.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"(?:kx_status|const char\s*\*)\s*(\w+)\s*\(", txt)))
+    return sorted(set(re.findall(r"(?:kx_status|size_t|const char\s*\*)\s*(\w+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
