@@ -1,0 +1,178 @@
+"""GPU parity at the full grid sizes of the larger workloads (MI355X only).
+
+The 120^3 HSE grid (K-step count 30), the 96 x 96 x 160 slab with a Dirichlet
+axis along the vacuum (32 and 40 K steps), the 80^3 Bloch grid of the k-point
+set in complex128 and complex64 (20 K steps), and the 90^3 system of the
+uneven batch (24 K steps): a few bands each, so the oracle stays cheap, every
+element of Vx compared with the oracle.  Bars as in the other parity tests:
+FP64 <= 1e-12 relative on Vx and E_x; FP32 and split-BF16 x6 <= 1e-6 relative
+on Vx and <= 1e-6 Ha per nominal atom (2 sum(g) / 14) on E_x.
+"""
+
+import numpy as np
+import pytest
+
+from oracle.exx import exchange_energy, vx_apply
+from oracle.kron import KronSolver
+from paper_2501_16572_amd.workloads import (CONFIGS, bloch_class, fermi_occupations, make_inputs,
+                                            monkhorst_pack, random_orbitals)
+
+from gpu_util import rel_fro, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BCP = ("periodic",) * 3
+
+
+@pytest.fixture(scope="module")
+def kx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_16572_amd import kronx
+    kronx.load_library()
+    return kronx
+
+
+def _tol(prec):
+    return 1e-12 if prec == "fp64" else 1e-6
+
+
+def _device_exx(kx, plan, psi_occ, occ, phi, g_phi, dt, vdt):
+    psid = to_dev(psi_occ, dt)
+    phid = to_dev(phi, dt)
+    occd = to_dev(occ, torch.float64)
+    gd = to_dev(g_phi, torch.float64)
+    vx = torch.zeros(phid.shape, dtype=vdt, device="cuda")
+    ex = torch.zeros(1, dtype=torch.float64, device="cuda")
+    kx.exx_apply(plan, psid, occd, phid, vx, ex=ex, gphi=gd)
+    torch.cuda.synchronize()
+    return to_host(vx), float(ex.item())
+
+
+def _check(prec, W, Ex, Wref, Eref, g_all):
+    err = rel_fro(W, Wref)
+    assert err <= _tol(prec), (prec, err)
+    if prec == "fp64":
+        assert abs(Ex - Eref) <= 1e-12 * abs(Eref), (Ex, Eref)
+    else:
+        atoms = 2.0 * float(np.sum(g_all)) / 14.0
+        assert abs(Ex - Eref) / atoms <= 1e-6, (Ex, Eref, atoms)
+
+
+GAMMA_CASES = {
+    # name: (config to take grid / spacing / BC / kernel from, or an explicit tuple)
+    "hse120": CONFIGS["hse120"],
+    "slab96": CONFIGS["slab96"],
+    "sys90": dict(n=(90, 90, 90), h=(0.25, 0.25, 0.25), bc=BCP, order=12, omega=0.106, n_b=192,
+                  n_occ=144, occ="fermi", kT=0.01, seed=56),
+}
+
+
+@pytest.fixture(scope="module")
+def gamma_inputs():
+    """Seven bands of each grid (five occupied) and the oracle's Vx, E_x."""
+    out = {}
+    for name, cfg in GAMMA_CASES.items():
+        psi, _ = make_inputs(cfg, n_b=7)
+        g = fermi_occupations(7, 5, 0.01, seed=cfg["seed"])
+        out[name] = (cfg, psi, g)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
+@pytest.mark.parametrize("name", list(GAMMA_CASES))
+def test_gamma_full_grid(kx, gamma_inputs, name, prec):
+    cfg, psi, g = gamma_inputs[name]
+    n_occ = 5
+    say("full grid", name, cfg["n"], cfg["bc"], prec)
+    psi_in = psi if prec == "fp64" else psi.astype(np.float32).astype(np.float64)
+    S = KronSolver(cfg["n"], cfg["h"], cfg["bc"], 12, cfg["omega"])
+    Wref = vx_apply(psi_in[:n_occ], g[:n_occ], psi_in, S)
+    Eref = exchange_energy(psi_in, g, Wref, S.dV)
+    plan = kx.kron_setup(cfg["n"], cfg["h"], cfg["bc"], 12, cfg["omega"], prec=prec)
+    try:
+        W, Ex = _device_exx(kx, plan, psi_in[:n_occ], g[:n_occ], psi_in, g, plan.dtype, torch.float64)
+    finally:
+        plan.destroy()
+    _check(prec, W, Ex, Wref, Eref, g)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("pair", [(0, 1), (3, 0), (2, 2)])
+def test_bloch80_full_grid(kx, prec, pair):
+    # one (k, q) block of the 2x2x1 Monkhorst-Pack set on the 80^3 grid,
+    # Coulomb kernel: targets at k, occupied orbitals at q, Bloch vector k - q
+    # (the plan takes its class modulo reciprocal vectors, the oracle the
+    # vector itself: the FD operator depends on it only through e^{i kappa L})
+    kg = CONFIGS["batch5"]["kgrid"]
+    n, h = kg["n"], kg["h"]
+    ks, _ = monkhorst_pack(n, h, kg["mp"])
+    ik, iq = pair
+    say("bloch 80^3", prec, "k", ik, "q", iq)
+    psi_k = random_orbitals(n, h, 4, seed=61 + ik, kpt=ks[ik])
+    psi_q = random_orbitals(n, h, 4, seed=61 + iq, kpt=ks[iq])
+    g_k = fermi_occupations(4, 3, 0.01, seed=71 + ik)
+    g_q = fermi_occupations(4, 3, 0.01, seed=71 + iq)
+    if prec == "fp32":
+        psi_k = psi_k.astype(np.complex64).astype(np.complex128)
+        psi_q = psi_q.astype(np.complex64).astype(np.complex128)
+    kappa = tuple(ks[ik][d] - ks[iq][d] for d in range(3))
+    S = KronSolver(n, h, BCP, 12, kg["omega"], kappa=kappa)
+    occ = 0.25 * g_q[:3]
+    Wref = vx_apply(psi_q[:3], occ, psi_k, S)
+    Eref = exchange_energy(psi_k, 0.25 * g_k, Wref, S.dV)
+    plan = kx.kron_setup(n, h, BCP, 12, kg["omega"], kq=bloch_class(kappa, n, h), prec=prec, complex=True)
+    try:
+        W, Ex = _device_exx(kx, plan, psi_q[:3], occ, psi_k, 0.25 * g_k, plan.dtype, torch.complex128)
+    finally:
+        plan.destroy()
+    _check(prec, W, Ex, Wref, Eref, 0.25 * g_k)
+
+
+def _forced_plan(kx, n, h, bc, omega, prec, bits, psi_d, occ_d, cache):
+    """A plan whose three passes run launch variant `bits`, set through the
+    tuning cache (its key comes from a first tuning run on the same shape)."""
+    if not cache.exists():
+        p0 = kx.kron_setup(n, h, bc, 12, omega, prec=prec)
+        kx.kx_autotune(p0, psi_d[:occ_d.shape[0]], occ_d, psi_d)
+        p0.destroy()
+    key = cache.read_text().split()[0]
+    with open(cache, "a") as f:
+        f.write(f"{key} {bits} 0 {bits} 0 {bits} 0\n")
+    plan = kx.kron_setup(n, h, bc, 12, omega, prec=prec)
+    kx.kx_autotune(plan, psi_d[:occ_d.shape[0]], occ_d, psi_d)
+    assert plan.tuning()["A"] == (bits, 0)
+    return plan
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["hse120", "slab96"])
+def test_every_launch_variant_full_grid(kx, name, prec, tmp_path, monkeypatch):
+    # variant bits 1 (occupancy), 2 (transposed mode-2 product), 4 (eigenvector
+    # matrices in LDS where they fit, else the streamed kernel) at 30 K steps
+    # (120^3) and at 24 / 40 K steps (the slab's 96-point slices and
+    # 160-point Dirichlet pencils)
+    cfg = GAMMA_CASES[name]
+    monkeypatch.setenv("KX_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    psi, _ = make_inputs(cfg, n_b=3)
+    g = fermi_occupations(3, 2, 0.01, seed=97)
+    psi_in = psi if prec == "fp64" else psi.astype(np.float32).astype(np.float64)
+    S = KronSolver(cfg["n"], cfg["h"], cfg["bc"], 12, cfg["omega"])
+    W = vx_apply(psi_in[:2], g[:2], psi_in, S)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    psid = to_dev(psi_in, dt)
+    occ = to_dev(g[:2], torch.float64)
+    cache = tmp_path / "tune.txt"
+    for bits in (0, 1, 2, 3, 4):
+        say("variant", name, prec, bits)
+        plan = _forced_plan(kx, cfg["n"], cfg["h"], cfg["bc"], cfg["omega"], prec, bits, psid, occ, cache)
+        try:
+            vx = torch.zeros(psid.shape, dtype=torch.float64, device="cuda")
+            kx.exx_apply(plan, psid[:2], occ, psid, vx)
+            torch.cuda.synchronize()
+            err = rel_fro(to_host(vx), W)
+            assert err < _tol(prec), (bits, err)
+        finally:
+            plan.destroy()
