@@ -229,10 +229,12 @@ size_t workspace_limit() {
     long long mb = std::atoll(env);
     if (mb > 0) return (size_t)mb << 20;
   }
+  // 60 % of the free device memory: on a 288 GB device a whole band block
+  // of a 120^3 FP64 workload (32 targets x 320 occupied, 141 GB) fits one
+  // batch, which the pass-C item count needs to fill the chip evenly
   size_t free_b = 0, total_b = 0;
-  size_t lim = (size_t)32 << 30;
-  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
-    lim = std::min(lim, free_b / 5 * 2);
+  size_t lim = (size_t)4 << 30;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) lim = free_b / 5 * 3;
   return std::max(lim, (size_t)64 << 20);
 }
 
@@ -375,6 +377,16 @@ hipError_t launch_pass_c(kx_plan p, int variant, const kx::AccArgs& C0, int64_t 
                              p->bf_kp12, s, tt);
 }
 
+// Blocks of plan p's pass-C persistent grid (its tuned configuration), asked
+// of the launcher without launching; the device's CU count if it has none.
+int64_t pass_c_grid(kx_plan p) {
+  int64_t g = 0;
+  kx::g_grid_probe = &g;
+  (void)launch_pass_c(p, kx::SI_ACC12, kx::AccArgs{}, (int64_t)1 << 40, nullptr);
+  kx::g_grid_probe = nullptr;
+  return g > 0 ? g : kx::device_cu_count();
+}
+
 // Plans whose batches can share one launch of pass `pass` (0 = A, 1 = B,
 // 2 = C) have equal keys: same kernel family, element type, tile count and
 // tuned variant.
@@ -445,9 +457,31 @@ int held_batch(const kx_plan p, int n_occ, int n_b) {
 
 // Enqueue one exx_apply.  Arguments already validated; buffers allocated for
 // the batch size returned by batch_targets().
+//
+// Pass C has one work item per (target, slice) and its persistent grid holds
+// R blocks at once, so a batch of t targets takes ceil(t n3 / R) rounds of
+// items, each round as long as one item (a loop over all occupied orbitals):
+// at 120^3 in FP64 (R = 256) a batch of 7 targets runs 4 rounds for 3.3
+// rounds of work.  Among the batch sizes the workspace limit allows, take
+// the one with the fewest pass-C rounds over all batches (a small charge per
+// batch for its launches breaks ties toward fewer batches).
 int batch_targets(kx_plan p, int n_occ, int n_b) {
   const size_t per_t = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
-  return balanced_batch(n_b, workspace_limit() / std::max<size_t>(per_t, 1));
+  const int cap = (int)std::max<size_t>(1, std::min<size_t>(workspace_limit() / std::max<size_t>(per_t, 1),
+                                                            (size_t)n_b));
+  const int64_t R = std::max<int64_t>(1, pass_c_grid(p));
+  const int64_t n3 = p->n[2];
+  int best = balanced_batch(n_b, cap);
+  double best_cost = 1e300;
+  for (int nt = cap; nt >= 1 && nt * 4 >= cap; --nt) {
+    const int k = (n_b + nt - 1) / nt, last = n_b - (k - 1) * nt;
+    const double cost = (double)(k - 1) * ((nt * n3 + R - 1) / R) + (double)((last * n3 + R - 1) / R) + 0.05 * k;
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = nt;
+    }
+  }
+  return best;
 }
 
 kx_status prepare_exx(kx_plan p, int n_occ, int n_b, int path) {

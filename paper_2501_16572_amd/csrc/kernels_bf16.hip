@@ -642,6 +642,10 @@ hipError_t inv_nt(int variant, const AccArgs& a, int64_t items, int max_blocks, 
                                            : variant == SI_ACC12 ? k_slice_inv_bf<SPL, NT, SPW, true>
                                                                  : k_slice_inv_bf<SPL, NT, SPW, false>;
   if (items <= 0) return hipSuccess;
+  if (g_grid_probe) {
+    *g_grid_probe = bf_grid(k, TH, items, max_blocks);
+    return hipSuccess;
+  }
   hipLaunchKernelGGL(k, dim3(bf_grid(k, TH, items, max_blocks)), dim3(TH), 0, s, a, vps, kpv, tt);
   return hipGetLastError();
 }

@@ -546,6 +546,10 @@ hipError_t cinv(int variant, const AccArgs& a, int64_t items, int max_blocks, hi
     if (items <= 0) return hipSuccess;
     int64_t cap = (int64_t)c_resident(k, TH) * device_cu_count();
     if (max_blocks > 0) cap = std::min<int64_t>(cap, max_blocks);
+    if (g_grid_probe) {
+      *g_grid_probe = std::max<int64_t>(1, std::min(items, cap));
+      return hipSuccess;
+    }
     hipLaunchKernelGGL(k, dim3((unsigned)std::max<int64_t>(1, std::min(items, cap))), dim3(TH), 0, s, a, tt);
     return hipGetLastError();
   }

@@ -6,6 +6,8 @@
 
 namespace kx {
 
+thread_local int64_t* g_grid_probe = nullptr;
+
 hipError_t launch_scale_f64(double* T, int64_t ld, int npairs, int64_t N, const double* ftab,
                             hipStream_t s) {
   if (npairs <= 0) return hipSuccess;

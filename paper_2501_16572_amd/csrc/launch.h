@@ -101,4 +101,9 @@ hipError_t launch_gemm_nn_f64(int m, int n, int k, const double* A, int64_t lda,
 // Number of compute units of the current device (cached).
 int device_cu_count();
 
+// When non-null, the inverse-slice (pass C) launchers store in *g_grid_probe
+// the grid they would launch for the given item count and launch nothing
+// (the batch-size choice asks how many pass-C blocks are resident at once).
+extern thread_local int64_t* g_grid_probe;
+
 }  // namespace kx
