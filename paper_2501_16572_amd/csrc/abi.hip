@@ -301,12 +301,14 @@ int tuned_blocks(const kx_plan p, int pass) {
 }
 // Launch variant bits of pass `pass` (bit 0: alternative occupancy target;
 // bit 1: transposed mode-2 product, passes A and C; bit 2: eigenvector
-// matrices resident in LDS, passes B and C) for the FP64/FP32 real kernels;
-// the other kernel families have one variant.
+// matrices resident in LDS, passes B and C; bit 3: register hand-off, pass
+// B) for the FP64/FP32 real kernels; the other kernel families have one
+// variant.
 int tuned_variant(const kx_plan p, int pass, int variant) {
   const bool real_mfma = !p->cplx && (p->prec == KX_PREC_FP64 || p->prec == KX_PREC_FP32);
   if (!real_mfma) return variant;
   const int bits = p->tune_tv[pass];
+  if ((bits & 8) && pass == 1) return variant | kx::TUNE_RH;
   if ((bits & 4) && pass != 0) return variant | kx::TUNE_VL;
   if (bits & 1) variant |= kx::TUNE_ALT;
   if ((bits & 2) && pass != 1) variant |= kx::TUNE_TR;
@@ -1160,8 +1162,8 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
   // FP64/FP32 real kernels only
   static const int cand[][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {0, 4}, {1, 0}, {1, 1}, {1, 2},
                                 {1, 3}, {1, 4}, {2, 0}, {2, 1}, {2, 2}, {2, 3}, {2, 4}, {3, 0},
-                                {3, 1}, {3, 2}, {3, 3}, {3, 4}, {4, 0}, {4, 1}, {4, 2}};
-  const int ncand = real_mfma ? 23 : 5;
+                                {3, 1}, {3, 2}, {3, 3}, {3, 4}, {4, 0}, {4, 1}, {4, 2}, {8, 0}};
+  const int ncand = real_mfma ? 24 : 5;
   hipEvent_t ev[4];
   for (int i = 0; i < 4; ++i) hipEventCreate(&ev[i]);
   float best[3] = {1e30f, 1e30f, 1e30f};

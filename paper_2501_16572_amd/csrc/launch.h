@@ -24,7 +24,9 @@ enum SliceFwdVariant { SF_PAIR12 = 0, SF_LOAD12, SF_PAIR, SF_LOAD1, SF_LOAD2 };
 // mode-2 product of the slice passes (x1 along the MFMA columns).
 // TUNE_VL selects the pass-B / pass-C kernels with the eigenvector matrices
 // resident in LDS (where they fit; elsewhere the streamed kernel runs).
-enum { TUNE_ALT = 64, TUNE_TR = 128, TUNE_VL = 256 };
+// TUNE_RH selects the register hand-off kernels (the second product of a
+// pass takes the first one's accumulators as its operand; kernels_rh.inc).
+enum { TUNE_ALT = 64, TUNE_TR = 128, TUNE_VL = 256, TUNE_RH = 512 };
 enum PencilVariant { PC_FSI = 0, PC_F, PC_I };
 enum SliceInvVariant { SI_ACC12 = 0, SI_ST12, SI_ST2, SI_ST1 };
 

@@ -151,7 +151,8 @@ def _forced_plan(kx, n, h, bc, omega, prec, bits, psi_d, occ_d, cache):
 @pytest.mark.parametrize("name", ["hse120", "slab96"])
 def test_every_launch_variant_full_grid(kx, name, prec, tmp_path, monkeypatch):
     # variant bits 1 (occupancy), 2 (transposed mode-2 product), 4 (eigenvector
-    # matrices in LDS where they fit, else the streamed kernel) at 30 K steps
+    # matrices in LDS where they fit, else the streamed kernel), 8 (register
+    # hand-off where its LDS matrix fits, else the streamed kernel) at 30 K steps
     # (120^3) and at 24 / 40 K steps (the slab's 96-point slices and
     # 160-point Dirichlet pencils)
     cfg = GAMMA_CASES[name]
@@ -165,7 +166,7 @@ def test_every_launch_variant_full_grid(kx, name, prec, tmp_path, monkeypatch):
     psid = to_dev(psi_in, dt)
     occ = to_dev(g[:2], torch.float64)
     cache = tmp_path / "tune.txt"
-    for bits in (0, 1, 2, 3, 4):
+    for bits in (0, 1, 2, 3, 4, 8):
         say("variant", name, prec, bits)
         plan = _forced_plan(kx, cfg["n"], cfg["h"], cfg["bc"], cfg["omega"], prec, bits, psid, occ, cache)
         try:
