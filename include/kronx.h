@@ -193,24 +193,45 @@ typedef struct {
  * several systems of uneven grid sizes) as one captured HIP graph on
  * `stream` (the batched n_c-style scheduling of Sec. II.B over a whole task
  * list).  Each task is cut into batches of targets as exx_apply does; the
- * batches are scheduled in rounds, and in each round the batches of every
- * pass whose plans share a kernel instantiation (element type, tile count,
- * tuned launch configuration) run as ONE persistent launch that walks a task
- * table; a lone batch launches as in exx_apply.  Two batches of one plan, or
- * two batches with overlapping d_vx, never share a round, and overlapping
- * outputs accumulate in task order.  The first call with a given task list
- * captures the graph (and allocates its task tables); later calls with the
- * same plans, pointers and sizes replay it.  All plans must share one
- * precision.  Results are bitwise reproducible across replays. */
+ * batches are scheduled in rounds such that two batches of one plan, or two
+ * batches with overlapping d_vx, never share a round (overlapping outputs
+ * accumulate in task order).
+ *   Work-queue form (FP64 / FP32 plans, real grids up to 120 points per axis
+ *   and complex grids up to 80): the graph is a counter reset and ONE
+ *   persistent launch in which every block takes tickets (a virtual block of
+ *   one pass of one batch, or a batch's E_x finalize) in order and waits on
+ *   device counters for what each ticket depends on.  A wait that gives up
+ *   (after about half a minute of polling; with KX_QUEUE_SPIN = r set, after
+ *   r + 1 polls) ends the launch early with incomplete results and is
+ *   reported by kx_batched_check.
+ *   Grouped form (otherwise, or with KX_BATCHED=rounds): in each round the
+ *   batches of every pass whose plans share a kernel instantiation run as
+ *   one persistent launch that walks a task table.
+ * The list's plans hold their workspaces at once and share one budget (60 %
+ * of the free device memory plus what they hold already, split in
+ * proportion to each plan's need for all its targets in one batch; a plan
+ * holding far more than its share gives the excess back), or
+ * KX_WORKSPACE_MB per plan when set.
+ * The first call with a given task list captures the graph (and allocates
+ * its tables); later calls with the same plans, pointers and sizes replay
+ * it.  All plans must share one precision.  Results are bitwise reproducible
+ * across replays. */
 kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream);
+
+/* kx_batched_check -- wait for `stream`, then KX_EDEVICE if the last
+ * work-queue replay of exx_apply_batched ended early (a dependency wait gave
+ * up), else KX_OK. */
+kx_status kx_batched_check(void* stream);
 
 /* kx_workspace_bytes -- device bytes that exx_apply (or a batched task) on
  * plan p with n_b targets and n_occ occupied orbitals holds: one batch of
  * pair intermediates (targets per batch x n_occ x N elements of the plan's
- * type, batches balanced within the workspace limit: min(32 GiB, 40 % of
- * free device memory) or KX_WORKSPACE_MB) plus the E_x partials.  The plan
- * allocates them at its first such call, grows them when a later call needs
- * more, and frees them in kron_destroy.  Host only, no allocation.
+ * type; within the workspace limit, 60 % of the free device memory or
+ * KX_WORKSPACE_MB, the batch size with the fewest rounds of pass-C items
+ * over the persistent grid) plus the E_x partials.  The plan allocates them
+ * at its first such call, grows them when a later call needs more (a
+ * batched call may also shrink them to its share), and frees them in
+ * kron_destroy.  Host only, no allocation.
  * *bytes = 0 when n_b or n_occ is 0. */
 kx_status kx_workspace_bytes(kx_plan p, int n_b, int n_occ, int64_t* bytes);
 
@@ -226,7 +247,8 @@ kx_status kx_graph_cache_info(int64_t out[3]);
 /* kx_batched_schedule -- shape of the schedule that the last capture of
  * exx_apply_batched in this process built: out[0] = rounds, out[1] = batches
  * (one task contributes ceil(n_b / targets per batch)), out[2] = launches of
- * the three fused passes, out[3] = the most batches that one launch ran.
+ * the three fused passes (1 in the work-queue form), out[3] = the most
+ * batches that one launch ran.
  * Host only; all zero before the first capture. */
 kx_status kx_batched_schedule(int out[4]);
 

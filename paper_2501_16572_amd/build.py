@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KX_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kernels_f64.hip", "kernels_f32.hip", "kernels_bf16.hip", "kernels_cplx.hip", "kernels_ace.hip", "kernels_slicewise.hip",
-           "abi.hip", "plan_host.cpp"]
+           "kernels_queue.hip", "abi.hip", "plan_host.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -24,6 +24,7 @@
 #include "../../include/kronx.h"
 #include "launch.h"
 #include "plan_host.h"
+#include "queue_plan.h"
 
 namespace {
 
@@ -157,9 +158,15 @@ struct kx_graph_entry {
   hipGraphExec_t exec;
   void* d_tables;                     // task tables of the grouped launches (device)
   uint64_t last_use;                  // replay clock of the last capture or replay
+  unsigned* d_err = nullptr;          // the work queue's error flag (queue form), in d_tables
 };
 
+// Error flag and stream of the last work-queue replay (kx_batched_check).
+unsigned* g_last_err = nullptr;
+hipStream_t g_last_err_stream = nullptr;
+
 void destroy_graph_entry(kx_graph_entry& g) {
+  if (g.d_err && g.d_err == g_last_err) g_last_err = nullptr;
   if (g.exec) hipGraphExecDestroy(g.exec);
   if (g.graph) hipGraphDestroy(g.graph);
   if (g.d_tables) hipFree(g.d_tables);
@@ -238,8 +245,11 @@ size_t workspace_limit() {
   return std::max(lim, (size_t)64 << 20);
 }
 
-kx_status ensure_buffer(void** ptr, size_t* have, size_t need, const char* what) {
-  if (*have >= need && *ptr) return KX_OK;
+// Device buffer of at least `need` bytes; with shrink, one holding more than
+// 5/4 of it (and 64 MiB more) is given back and allocated again at `need`.
+kx_status ensure_buffer(void** ptr, size_t* have, size_t need, const char* what, bool shrink = false) {
+  const bool oversized = shrink && *have > need / 4 * 5 + ((size_t)64 << 20);
+  if (*have >= need && *ptr && !oversized) return KX_OK;
   if (*ptr) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return dev_fail(e, "synchronize before regrow");
@@ -467,10 +477,12 @@ int held_batch(const kx_plan p, int n_occ, int n_b) {
 // rounds of work.  Among the batch sizes the workspace limit allows, take
 // the one with the fewest pass-C rounds over all batches (a small charge per
 // batch for its launches breaks ties toward fewer batches).
-int batch_targets(kx_plan p, int n_occ, int n_b) {
+//
+// limit: workspace bytes the plan may hold (0: workspace_limit()).
+int batch_targets(kx_plan p, int n_occ, int n_b, size_t limit = 0) {
+  if (!limit) limit = workspace_limit();
   const size_t per_t = (size_t)n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
-  const int cap = (int)std::max<size_t>(1, std::min<size_t>(workspace_limit() / std::max<size_t>(per_t, 1),
-                                                            (size_t)n_b));
+  const int cap = (int)std::max<size_t>(1, std::min<size_t>(limit / std::max<size_t>(per_t, 1), (size_t)n_b));
   const int64_t R = std::max<int64_t>(1, pass_c_grid(p));
   const int64_t n3 = p->n[2];
   int best = balanced_batch(n_b, cap);
@@ -486,12 +498,14 @@ int batch_targets(kx_plan p, int n_occ, int n_b) {
   return best;
 }
 
-kx_status prepare_exx(kx_plan p, int n_occ, int n_b, int path) {
-  const int nt = batch_targets(p, n_occ, n_b);
+// Buffers of plan p for calls with n_b targets x n_occ occupied (limit as
+// in batch_targets; shrink: give back a workspace far larger than that).
+kx_status prepare_exx(kx_plan p, int n_occ, int n_b, int path, size_t limit = 0, bool shrink = false) {
+  const int nt = batch_targets(p, n_occ, n_b, limit);
   const size_t eb = elem_bytes(p->prec) * (p->cplx ? 2 : 1);
   void* ws0 = p->d_ws;
   void* part0 = p->d_part;
-  kx_status st = ensure_buffer(&p->d_ws, &p->ws_bytes, (size_t)nt * n_occ * p->N * eb, "workspace");
+  kx_status st = ensure_buffer(&p->d_ws, &p->ws_bytes, (size_t)nt * n_occ * p->N * eb, "workspace", shrink);
   if (st != KX_OK) return st;
   const size_t per_t = std::max<size_t>(64, (size_t)p->n[2]);
   st = ensure_buffer((void**)&p->d_part, &p->part_bytes, (size_t)nt * per_t * sizeof(double),
@@ -1262,8 +1276,155 @@ std::vector<std::vector<SubTask>> schedule_rounds(const kx_task* tasks, int ntas
   return rounds;
 }
 
+// Workspaces of a batched call's plans.  Every plan of the list holds its
+// buffers at once, so they share one budget: KX_WORKSPACE_MB per plan when
+// set, else 60 % of the free device memory plus what these plans hold
+// already, split in proportion to what each plan would need for all its
+// targets in one batch (each gets that need when the budget covers them
+// all).  A plan's largest task sizes its buffers, which shrink when they
+// hold far more than its share (an earlier single call or autotuning may
+// have sized them for the plan alone).
+kx_status prepare_batched(const kx_task* tasks, int ntasks) {
+  std::vector<kx_plan> plans;
+  std::vector<size_t> need;
+  std::vector<int> big;  // task with the largest need, per plan
+  for (int i = 0; i < ntasks; ++i) {
+    const kx_task& t = tasks[i];
+    if (t.n_occ == 0 || t.n_b == 0) continue;
+    const kx_plan p = t.plan;
+    const size_t nd = (size_t)t.n_b * t.n_occ * p->N * elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+    size_t j = 0;
+    while (j < plans.size() && plans[j] != p) ++j;
+    if (j == plans.size()) {
+      plans.push_back(p);
+      need.push_back(nd);
+      big.push_back(i);
+    } else if (nd > need[j]) {
+      need[j] = nd;
+      big[j] = i;
+    }
+  }
+  std::vector<size_t> limit(plans.size(), 0);
+  const char* env = std::getenv("KX_WORKSPACE_MB");
+  if (!(env && *env && std::atoll(env) > 0)) {
+    size_t free_b = 0, total_b = 0, held = 0, sum = 0;
+    for (size_t j = 0; j < plans.size(); ++j) {
+      held += plans[j]->ws_bytes;
+      sum += need[j];
+    }
+    size_t budget = (size_t)4 << 30;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) budget = (free_b + held) / 5 * 3;
+    for (size_t j = 0; j < plans.size(); ++j)
+      limit[j] = std::max<size_t>((size_t)64 << 20,
+                                  sum <= budget ? need[j] : (size_t)((double)budget * need[j] / sum));
+  }
+  // each plan's largest task sizes its buffers: those that shrink first,
+  // then those that grow
+  for (int grow = 0; grow < 2; ++grow)
+    for (size_t j = 0; j < plans.size(); ++j) {
+      const kx_task& t = tasks[big[j]];
+      const kx_plan p = t.plan;
+      const size_t want = (size_t)batch_targets(p, t.n_occ, t.n_b, limit[j]) * t.n_occ * p->N *
+                          elem_bytes(p->prec) * (p->cplx ? 2 : 1);
+      if ((p->ws_bytes > want) == (grow == 1)) continue;
+      kx_status st = prepare_exx(p, t.n_occ, t.n_b, KX_PATH_FUSED, limit[j], limit[j] != 0);
+      if (st != KX_OK) return st;
+    }
+  for (int i = 0; i < ntasks; ++i) {
+    const kx_task& t = tasks[i];
+    if (t.n_occ == 0 || t.n_b == 0) continue;
+    size_t j = 0;
+    while (plans[j] != t.plan) ++j;
+    if (i == big[j]) continue;
+    kx_status st = prepare_exx(t.plan, t.n_occ, t.n_b, KX_PATH_FUSED, limit[j], false);
+    if (st != KX_OK) return st;
+  }
+  return KX_OK;
+}
+
 // Shape of the last captured schedule (kx_batched_schedule).
 int g_last_sched[4] = {0, 0, 0, 0};
+
+// The work-queue form of a schedule (one persistent launch, kernels_queue.hip):
+// its tile shape, or false when a plan needs an element type or a tile count
+// it has no instantiation for (the grouped-round form runs then).
+bool queue_eligible(const kx_task* tasks, int ntasks, bool* f64, int* nkr, int* nkc) {
+  const char* env = std::getenv("KX_BATCHED");
+  if (env && std::strcmp(env, "rounds") == 0) return false;
+  int nk_real = 1, nk_cplx = 1;
+  bool any = false;
+  for (int i = 0; i < ntasks; ++i) {
+    const kx_plan p = tasks[i].plan;
+    if (tasks[i].n_occ == 0 || tasks[i].n_b == 0) continue;
+    if (p->prec != KX_PREC_FP64 && p->prec != KX_PREC_FP32) return false;
+    const int nk = std::max(p->nk12, p->nk3);
+    (p->cplx ? nk_cplx : nk_real) = std::max(p->cplx ? nk_cplx : nk_real, nk);
+    *f64 = p->prec == KX_PREC_FP64;
+    any = true;
+  }
+  return any && kx::queue_shape(nk_real, nk_cplx, nkr, nkc);
+}
+
+// Tickets and argument tables of the work queue for the batches of `rounds`
+// (order and dependencies: queue_plan.h).  Virtual grids: passes A and C
+// spread over the queue's grid, pass B over a multiple of its pencil chunks.
+struct QueueBuild {
+  std::vector<kx::QTicket> tickets;
+  std::vector<kx::SliceArgs> sa;
+  std::vector<kx::PencilArgs> pa;
+  std::vector<kx::AccArgs> ca;
+  std::vector<kx::QFin> fa;
+  int nctr = 0;
+};
+QueueBuild build_queue(const kx_task* tasks, const std::vector<std::vector<SubTask>>& rounds, int grid) {
+  QueueBuild q;
+  std::vector<std::vector<kx::QBatchDesc>> desc;
+  std::vector<bool> cplx;
+  std::vector<int> fin_index;
+  std::vector<const kx_plan_s*> plan_ids;
+  for (const auto& round : rounds) {
+    desc.emplace_back();
+    for (const SubTask& st : round) {
+      const kx_task& t = tasks[st.task];
+      const kx_plan p = t.plan;
+      const size_t vxw = p->cplx ? 2 : 1;
+      const double* lo = t.d_vx + (size_t)st.n0 * t.ld_vx * vxw;
+      const double* hi = lo + (size_t)(st.cur - 1) * t.ld_vx * vxw + (size_t)p->N * vxw;
+      const BatchArgs ba = batch_args(p, t.d_psi, t.ld_psi, t.n_occ, t.d_occ, t.d_phi, t.ld_phi, t.d_vx, t.ld_vx,
+                                      t.d_ex != nullptr, st.n0, st.cur);
+      q.sa.push_back(kernel_args_a(p, ba.A));
+      q.pa.push_back(kernel_args_b(p, ba.B));
+      q.ca.push_back(kernel_args_c(p, ba.C));
+      fin_index.push_back(t.d_ex ? (int)q.fa.size() : -1);
+      if (t.d_ex) q.fa.push_back(kx::QFin{p->d_part, st.cur, p->n[2], t.d_gphi + st.n0, p->dV, t.d_ex});
+      cplx.push_back(p->cplx);
+      int pid = 0;
+      while (pid < (int)plan_ids.size() && plan_ids[pid] != p) ++pid;
+      if (pid == (int)plan_ids.size()) plan_ids.push_back(p);
+      const int64_t npairs = (int64_t)st.cur * t.n_occ;
+      const int nch = std::max(ba.B.nchunks, 1);
+      const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(npairs, grid / nch));
+      desc.back().push_back(kx::QBatchDesc{pid, (int)std::min<int64_t>(npairs * p->n[2], grid), (int)(groups * nch),
+                                           (int)std::min<int64_t>((int64_t)st.cur * p->n[2], grid), t.d_ex ? 1 : 0,
+                                           (uintptr_t)lo, (uintptr_t)hi});
+    }
+  }
+  for (const kx::QTicketDesc& d : kx::queue_tickets(desc)) {
+    kx::QTicket t{};
+    t.kind = d.pass == 3 ? kx::QK_FINAL : d.pass + (cplx[d.batch] ? kx::QK_CPLX_A : kx::QK_REAL_A);
+    t.arg = d.pass == 3 ? fin_index[d.batch] : d.batch;
+    t.vb = d.vb;
+    t.vg = d.vg;
+    t.done = d.done;
+    for (int i = 0; i < 3; ++i) {
+      t.dep[i] = d.dep[i];
+      t.need[i] = d.need[i];
+    }
+    q.tickets.push_back(t);
+  }
+  q.nctr = 4 * (int)cplx.size();
+  return q;
+}
 
 // One launch of the grouped schedule: pass `pass` over the batches `subs`.
 struct GroupLaunch {
@@ -1273,6 +1434,116 @@ struct GroupLaunch {
 };
 
 }  // namespace
+
+}  // extern "C"
+
+namespace {
+
+// Capture the work-queue form (a counter reset, then one persistent launch)
+// of a task list whose plans are prepared, cache and launch it.  Called with
+// g_graph_mu held.
+kx_status capture_queue(const kx_task* tasks, int ntasks, const std::vector<std::vector<SubTask>>& rounds,
+                        bool f64, int nkr, int nkc, hipStream_t s) {
+  const int grid = kx::queue_grid(f64, nkr, nkc);
+  if (grid < 1) return fail(KX_EDEVICE, "exx_apply_batched: no work-queue kernel for this shape");
+  const QueueBuild qb = build_queue(tasks, rounds, grid);
+  // one device block: tickets | slice args | pencil args | acc args | finalize
+  // args | counters | dispenser | error flag
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    const size_t at = off;
+    off += bytes;
+    return at;
+  };
+  const size_t o_t = place(qb.tickets.size() * sizeof(kx::QTicket));
+  const size_t o_sa = place(qb.sa.size() * sizeof(kx::SliceArgs));
+  const size_t o_pa = place(qb.pa.size() * sizeof(kx::PencilArgs));
+  const size_t o_ca = place(qb.ca.size() * sizeof(kx::AccArgs));
+  const size_t o_fa = place(std::max<size_t>(1, qb.fa.size()) * sizeof(kx::QFin));
+  const size_t o_ctr = place(std::max(1, qb.nctr) * sizeof(unsigned));
+  const size_t o_next = place(sizeof(unsigned));
+  const size_t o_err = place(sizeof(unsigned));
+  const size_t bytes = place(0);
+  std::vector<char> h(bytes, 0);
+  std::memcpy(h.data() + o_t, qb.tickets.data(), qb.tickets.size() * sizeof(kx::QTicket));
+  std::memcpy(h.data() + o_sa, qb.sa.data(), qb.sa.size() * sizeof(kx::SliceArgs));
+  std::memcpy(h.data() + o_pa, qb.pa.data(), qb.pa.size() * sizeof(kx::PencilArgs));
+  std::memcpy(h.data() + o_ca, qb.ca.data(), qb.ca.size() * sizeof(kx::AccArgs));
+  if (!qb.fa.empty()) std::memcpy(h.data() + o_fa, qb.fa.data(), qb.fa.size() * sizeof(kx::QFin));
+  char* d = nullptr;
+  hipError_t e = hipMalloc((void**)&d, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(KX_ENOMEM, "exx_apply_batched: work-queue tables");
+  }
+  e = hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(d);
+    return dev_fail(e, "exx_apply_batched: work-queue upload");
+  }
+  kx::QueueArgs qa{};
+  qa.tickets = (const kx::QTicket*)(d + o_t);
+  qa.ntickets = (int)qb.tickets.size();
+  qa.sa = (const kx::SliceArgs*)(d + o_sa);
+  qa.pa = (const kx::PencilArgs*)(d + o_pa);
+  qa.ca = (const kx::AccArgs*)(d + o_ca);
+  qa.fa = (const kx::QFin*)(d + o_fa);
+  qa.ctr = (unsigned*)(d + o_ctr);
+  qa.next = (unsigned*)(d + o_next);
+  qa.err = (unsigned*)(d + o_err);
+  qa.nctr = qb.nctr;
+  qa.spin_limit = 1 << 24;  // polls of ~2 us: a wait gives up after about half a minute
+  if (const char* env = std::getenv("KX_QUEUE_SPIN")) {  // 0: a wait not met at its first poll gives up
+    const long long v = std::atoll(env);
+    if (v >= 0 && *env) qa.spin_limit = v;
+  }
+  hipGraph_t graph = nullptr;
+  hipStream_t cap = nullptr;
+  e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) hipStreamDestroy(cap);
+  }
+  if (e != hipSuccess) {
+    hipFree(d);
+    return dev_fail(e, "exx_apply_batched capture");
+  }
+  e = kx::launch_queue(f64, nkr, nkc, qa, grid, cap);
+  hipError_t e2 = hipStreamEndCapture(cap, &graph);
+  hipStreamDestroy(cap);
+  if (e == hipSuccess) e = e2;
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    hipFree(d);
+    return dev_fail(e, "exx_apply_batched capture");
+  }
+  {
+    int nsub = 0;
+    for (const auto& r : rounds) nsub += (int)r.size();
+    g_last_sched[0] = (int)rounds.size();
+    g_last_sched[1] = nsub;
+    g_last_sched[2] = 1;
+    g_last_sched[3] = nsub;
+  }
+  std::vector<unsigned> gens(ntasks);
+  for (int i = 0; i < ntasks; ++i) gens[i] = tasks[i].plan->gen;
+  kx_graph_entry ge{std::vector<kx_task>(tasks, tasks + ntasks), gens, s, graph, exec, d, ++g_graph_clock};
+  ge.d_err = qa.err;
+  g_graphs.push_back(ge);
+  ++g_graph_captures;
+  e = hipGraphLaunch(exec, s);
+  if (e != hipSuccess) return dev_fail(e, "exx_apply_batched launch");
+  g_last_err = qa.err;
+  g_last_err_stream = s;
+  return KX_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
   if (ntasks < 0 || (ntasks > 0 && !tasks)) return fail(KX_EINVAL, "exx_apply_batched: bad task list");
@@ -1287,15 +1558,16 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
   }
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lock(g_graph_mu);
-  for (int i = 0; i < ntasks; ++i) {
-    const kx_task& t = tasks[i];
-    if (t.n_occ == 0 || t.n_b == 0) continue;
-    kx_status st = prepare_exx(t.plan, t.n_occ, t.n_b, KX_PATH_FUSED);
+  {
+    kx_status st = prepare_batched(tasks, ntasks);
     if (st != KX_OK) return st;
   }
+  bool qf64 = false;
+  int nkr = 0, nkc = 0;
+  const bool want_queue = queue_eligible(tasks, ntasks, &qf64, &nkr, &nkc);
   for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
     kx_graph_entry& g = *it;
-    if (g.stream != s || (int)g.tasks.size() != ntasks) continue;
+    if (g.stream != s || (int)g.tasks.size() != ntasks || (g.d_err != nullptr) != want_queue) continue;
     bool same = true;
     for (int i = 0; i < ntasks && same; ++i) same = same_task(g.tasks[i], tasks[i]);
     if (!same) continue;
@@ -1310,6 +1582,8 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
     g.last_use = ++g_graph_clock;
     hipError_t e = hipGraphLaunch(g.exec, s);
     if (e != hipSuccess) return dev_fail(e, "exx_apply_batched replay");
+    g_last_err = g.d_err;
+    g_last_err_stream = s;
     return KX_OK;
   }
   if (g_graphs.size() >= kGraphCacheCap) {
@@ -1321,10 +1595,11 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
     g_graphs.erase(lru);
   }
 
-  // Schedule: per round, the batches of each pass are grouped by kernel
+  const std::vector<std::vector<SubTask>> rounds = schedule_rounds(tasks, ntasks);
+  if (want_queue) return capture_queue(tasks, ntasks, rounds, qf64, nkr, nkc, s);
+  // Grouped rounds: per round, the batches of each pass are grouped by kernel
   // instantiation; a group of several batches is one persistent launch over
   // a task table, a single batch launches with its own arguments.
-  const std::vector<std::vector<SubTask>> rounds = schedule_rounds(tasks, ntasks);
   std::vector<GroupLaunch> launches;
   size_t tab_bytes = 0;
   auto arg_size = [](int pass) {
@@ -1602,6 +1877,22 @@ kx_status kx_graph_cache_info(int64_t out[3]) {
   out[0] = (int64_t)g_graphs.size();
   out[1] = (int64_t)kGraphCacheCap;
   out[2] = (int64_t)g_graph_captures;
+  return KX_OK;
+}
+
+kx_status kx_batched_check(void* stream) {
+  unsigned* err = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    err = g_last_err;
+  }
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return dev_fail(e, "kx_batched_check");
+  if (!err) return KX_OK;
+  unsigned v = 0;
+  e = hipMemcpy(&v, err, sizeof(v), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return dev_fail(e, "kx_batched_check");
+  if (v) return fail(KX_EDEVICE, "exx_apply_batched: a work-queue wait gave up; results are incomplete");
   return KX_OK;
 }
 

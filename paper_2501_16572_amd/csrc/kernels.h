@@ -81,6 +81,40 @@ struct TaskTab {
   int ntasks;
 };
 
+// Work queue of the batched entry point (one persistent launch for a whole
+// task list).  A ticket is one virtual block (vb of a virtual grid of vg
+// blocks) of one pass of one batch, or the E_x finalize of a batch; blocks
+// take tickets in order from a shared counter, wait until the counters named
+// in dep[] have reached need[], run the ticket and increment counter `done`.
+// Every dependency is on tickets with a smaller number, which were taken by
+// running blocks, so every wait ends; each wait is also bounded (spin_limit
+// polls), and a wait that gives up sets *err and ends its block.
+enum QKind { QK_REAL_A = 0, QK_REAL_B, QK_REAL_C, QK_CPLX_A, QK_CPLX_B, QK_CPLX_C, QK_FINAL };
+struct QTicket {
+  int kind, arg, vb, vg, done;
+  int dep[3], need[3];
+};
+struct QFin {  // E_x finalize: *ex += dV sum_t gphi[t] sum_j partials[t * per_target + j]
+  const double* partials;
+  int n_t, per_target;
+  const double* gphi;
+  double dV;
+  double* ex;
+};
+struct QueueArgs {
+  const QTicket* tickets;
+  int ntickets;
+  const SliceArgs* sa;
+  const PencilArgs* pa;
+  const AccArgs* ca;
+  const QFin* fa;
+  unsigned* next;         // ticket dispenser
+  unsigned* ctr;          // completion counters
+  unsigned* err;          // nonzero once a wait gave up
+  int nctr;
+  long long spin_limit;   // retries after a wait's first poll (each after a sleep of ~2 us)
+};
+
 // Entry of flat item g: its index, a copy of its argument struct, and the
 // item's index within it.  The table is read through the constant address
 // space (it does not change during a launch), so the loads are scalar and the

@@ -103,6 +103,15 @@ hipError_t launch_gemm_nn_f64(int m, int n, int k, const double* A, int64_t lda,
 // Number of compute units of the current device (cached).
 int device_cu_count();
 
+// Work-queue kernel of the batched entry point (kernels_queue.hip).
+// queue_shape: the instantiated tile counts covering real plans of up to
+// nk_real K steps and complex plans of up to nk_cplx (false: none);
+// queue_grid: its co-resident blocks on the device; launch_queue: a counter
+// reset kernel, then the queue over `grid` blocks.
+bool queue_shape(int nk_real, int nk_cplx, int* nkr, int* nkc);
+int queue_grid(bool f64, int nkr, int nkc);
+hipError_t launch_queue(bool f64, int nkr, int nkc, const QueueArgs& q, int grid, hipStream_t s);
+
 // When non-null, the inverse-slice (pass C) launchers store in *g_grid_probe
 // the grid they would launch for the given item count and launch nothing
 // (the batch-size choice asks how many pass-C blocks are resident at once).

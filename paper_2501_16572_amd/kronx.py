@@ -35,7 +35,7 @@ EXPORTS = ["kron_setup", "kron_destroy", "kron_solve", "exx_apply", "exx_apply_b
            "kx_last_error", "kx_trace_enable", "kx_trace_read", "kx_trace_name", "kx_autotune",
            "kx_plan_tuning", "kx_batched_schedule", "kx_workspace_bytes", "kx_ace_workspace_bytes",
            "ace_construct", "ace_apply", "kx_graph_cache_info", "exx_apply_static",
-           "kx_static_scratch_bytes"]
+           "kx_static_scratch_bytes", "kx_batched_check"]
 
 
 class KronxError(RuntimeError):
@@ -75,6 +75,7 @@ def load_library(path=None):
     lib.exx_apply_static.argtypes = [vp, vp, i64, ci, vp, vp, i64, ci, vp, i64, vp, vp, ci, vp]
     lib.kx_static_scratch_bytes.argtypes = []
     lib.exx_apply_batched.argtypes = [ctypes.POINTER(_Task), ci, vp]
+    lib.kx_batched_check.argtypes = [vp]
     lib.kx_plan_info.argtypes = [vp, i64p]
     lib.kx_plan_tables.argtypes = [vp, ci, dp, dp, dp]
     lib.kx_host_eig1d.argtypes = [ci, cd, ci, ci, cd, dp, dp, dp]
@@ -348,6 +349,11 @@ def kx_autotune(plan, psi, occ, phi, stream=None):
                                     phi.shape[0], _stream(stream))
     _check(st, "kx_autotune")
     return plan.tuning()
+
+
+def kx_batched_check(stream=None):
+    """Wait for the stream; raise if the last work-queue replay ended early."""
+    _check(load_library().kx_batched_check(_stream(stream)), "kx_batched_check")
 
 
 def exx_apply_batched(tasks, stream=None):

@@ -153,23 +153,28 @@ def bloch_class(kq, n, h):
     return tuple(out)
 
 
-def make_batch_inputs(cfg):
+def make_batch_inputs(cfg, progress=None):
     """Inputs of the batched workload.
 
     Returns (kpart, systems): kpart = dict(kpts, wk, psi (list of (n_b, N)
     complex128), g (list of (n_b,))); systems = list of dicts with n, h, psi
-    (n_b, N) float64, g (n_b,) and n_occ.
+    (n_b, N) float64, g (n_b,) and n_occ.  ``progress`` (optional callable)
+    is called with a short text before each set of orbitals is drawn.
     """
     kg = cfg["kgrid"]
     ks, wk = monkhorst_pack(kg["n"], kg["h"], kg["mp"])
     rng = np.random.default_rng(kg["seed"])
     psi_k, g_k = [], []
-    for k in ks:
+    for ik, k in enumerate(ks):
+        if progress:
+            progress(f"orbitals of k-point {ik}")
         psi_k.append(random_orbitals(kg["n"], kg["h"], kg["n_b"], seed=None, rng=rng, kpt=k))
         g_k.append(fermi_occupations(kg["n_b"], kg["n_occ"], kg["kT"], seed=None, rng=rng))
     kpart = dict(kpts=ks, wk=wk, psi=psi_k, g=g_k, n_occ=kg["n_occ"])
     systems = []
     for i, (n, nb, no) in enumerate(cfg["systems"]):
+        if progress:
+            progress(f"orbitals of system {i} ({n})")
         rng = np.random.default_rng(cfg["seed"] + i)
         h = (cfg["h"],) * 3
         psi = random_orbitals(n, h, nb, seed=None, rng=rng)

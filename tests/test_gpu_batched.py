@@ -1,12 +1,15 @@
-"""Batched exchange (exx_apply_batched) with grouped persistent launches.
+"""Batched exchange (exx_apply_batched): the work-queue form (one persistent
+launch per call) and the grouped-round form (KX_BATCHED=rounds; split-BF16
+plans always).
 
-Batches of several tasks whose plans share a kernel instantiation run as one
-launch over a task table.  Each item of such a launch does the arithmetic of
-the single-batch kernel in the same order, so the batched results are compared
-with per-task exx_apply calls (FP64 to 1e-14 relative, FP32 / split-BF16 to
-1e-6 of the FP64 scale), and the k-point set against the FP64 oracle
-(1e-12 / 1e-6).  The schedule shape (rounds, launches, widest launch) is
-checked through kx_batched_schedule so that grouping is known to happen.
+Both forms run the pass bodies of the single-batch kernels item by item, so
+the batched results are compared with per-task exx_apply calls (FP64 to 1e-14
+relative, FP32 / split-BF16 to 1e-6 of the FP64 scale) and with the FP64
+oracle (1e-12 / 1e-6 on Vx, E_x relative 1e-12 or 1e-6 Ha per nominal atom).
+The schedule shape (rounds, batches, launches, widest launch) is checked
+through kx_batched_schedule so that the form that ran is known.  The queue's
+bounded waits are checked by a tiny poll budget set from the host
+(KX_QUEUE_SPIN): the launch ends early and kx_batched_check reports it.
 """
 
 import numpy as np
@@ -45,13 +48,16 @@ def _rel(a, b):
     return float((a - b).norm() / max(float(b.norm()), 1e-300))
 
 
+@pytest.mark.parametrize("form", ["queue", "rounds"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_kpoint_set_one_launch_per_round(kx, prec):
+def test_kpoint_set_batched(kx, prec, form, monkeypatch):
     # 2 k-points x 2 q-points on one grid: four complex plans (one per k - q).
-    # Tasks of one k write the same Vx, so the schedule has two rounds, each
-    # running two batches per pass in a single launch.
+    # Tasks of one k write the same Vx, so the schedule has two rounds of two
+    # batches: one queue launch for all of them, or per round one launch per
+    # pass holding both batches.
     n, h = (16, 18, 14), (0.35, 0.35, 0.35)
-    say("batched k-points", prec)
+    say("batched k-points", prec, form)
+    monkeypatch.setenv("KX_BATCHED", form)
     L = [n[d] * h[d] for d in range(3)]
     kpts = [(2 * np.pi / L[0] * 0.25, 2 * np.pi / L[1] * 0.25, 0.0),
             (-2 * np.pi / L[0] * 0.25, 2 * np.pi / L[1] * 0.25, 0.0)]
@@ -85,8 +91,8 @@ def test_kpoint_set_one_launch_per_round(kx, prec):
             kx.exx_apply_batched(tasks)
             torch.cuda.synchronize()
             results.append(([to_host(v) for v in vx], [float(to_host(e)[0]) for e in ex]))
-        rounds, batches, launches, widest = kx.kx_batched_schedule()
-        assert (rounds, batches, launches, widest) == (2, 4, 6, 2), (rounds, batches, launches, widest)
+        sched = kx.kx_batched_schedule()
+        assert sched == ((2, 4, 1, 4) if form == "queue" else (2, 4, 6, 2)), sched
     finally:
         for p in plans:
             p.destroy()
@@ -146,14 +152,16 @@ def _oracle_systems(prec, systems):
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
-def test_uneven_systems_ragged_batches(kx, prec, monkeypatch):
+@pytest.mark.parametrize("prec,form", [("fp64", "queue"), ("fp64", "rounds"), ("fp32", "queue"),
+                                       ("fp32", "rounds"), ("bf16x6", "rounds")])
+def test_uneven_systems_ragged_batches(kx, prec, form, monkeypatch):
     # a small workspace cuts every task into several batches of uneven size,
     # so rounds hold batches of different systems and ragged last batches;
     # every replay against the FP64 oracle (FP64 1e-12, mixed 1e-6 on Vx and
     # 1e-6 Ha per nominal atom on E_x) and against per-task exx_apply calls
-    say("batched uneven systems", prec)
+    say("batched uneven systems", prec, form)
     monkeypatch.setenv("KX_WORKSPACE_MB", "1")
+    monkeypatch.setenv("KX_BATCHED", form)
     plans, tasks = _gamma_tasks(kx, prec, SYSTEMS)
     ora = _oracle_systems(prec, SYSTEMS)
     try:
@@ -176,7 +184,10 @@ def test_uneven_systems_ragged_batches(kx, prec, monkeypatch):
                     assert err < 1e-6 and dE / atoms < 1e-6, (rep, i, err, dE / atoms)
         rounds, batches, launches, widest = kx.kx_batched_schedule()
         assert batches > len(SYSTEMS) and rounds >= 2
-        assert widest >= 2 and launches < 3 * batches, (rounds, batches, launches, widest)
+        if form == "queue":
+            assert launches == 1 and widest == batches, (rounds, batches, launches, widest)
+        else:
+            assert widest >= 2 and launches < 3 * batches, (rounds, batches, launches, widest)
     finally:
         for p in plans:
             p.destroy()
@@ -290,3 +301,83 @@ def test_graph_cache_bounded_and_retuned(kx, tmp_path, monkeypatch):
         assert rel_fro(to_host(outs[-1]), to_host(vx_e)) < 1e-13
     finally:
         plan.destroy()
+
+
+def test_queue_matches_rounds_and_shares_plans(kx, monkeypatch):
+    # one list through both forms: two Gamma systems, one of them split over
+    # two tasks of one plan (its halves never overlap in the queue), small
+    # workspace for several batches each; FP64 results of the two forms agree
+    # to 1e-14 and both match the oracle
+    say("queue vs rounds")
+    monkeypatch.setenv("KX_WORKSPACE_MB", "1")
+    systems = [SYSTEMS[0], SYSTEMS[2]]
+    plans, tasks = _gamma_tasks(kx, "fp64", systems)
+    ora = _oracle_systems("fp64", systems)
+    try:
+        t0 = tasks[0]
+        half = t0["phi"].shape[0] // 2
+        split = [dict(t0, phi=t0["phi"][:half], vx=t0["vx"][:half], gphi=t0["gphi"][:half]),
+                 tasks[1],
+                 dict(t0, phi=t0["phi"][half:], vx=t0["vx"][half:], gphi=t0["gphi"][half:])]
+        out = {}
+        for form in ("queue", "rounds"):
+            monkeypatch.setenv("KX_BATCHED", form)
+            for t in tasks:
+                t["vx"].zero_()
+                t["ex"].zero_()
+            kx.exx_apply_batched(split)
+            kx.kx_batched_check()
+            torch.cuda.synchronize()
+            sched = kx.kx_batched_schedule()
+            assert (sched[2] == 1) == (form == "queue"), (form, sched)
+            out[form] = [(t["vx"].clone(), t["ex"].clone()) for t in tasks]
+        for (vq, eq), (vr, er), (W, E, _) in zip(out["queue"], out["rounds"], ora):
+            assert _rel(vq, vr) < 1e-14
+            assert abs(float(eq[0] - er[0])) <= 1e-14 * abs(float(er[0]))
+            assert rel_fro(to_host(vq), W) < 1e-12
+            assert abs(float(eq[0]) - E) < 1e-12 * abs(E)
+    finally:
+        for p in plans:
+            p.destroy()
+
+
+def test_queue_bounded_wait_reports_and_recovers(kx, monkeypatch):
+    # a poll budget of no retries (KX_QUEUE_SPIN=0, set from the host): one
+    # batch whose pass A has a ticket per block, so the first block to take a
+    # pass-B ticket finds the other blocks' pass-A tickets still running; its
+    # wait gives up, the error flag ends every block at its next ticket, the
+    # launch returns and kx_batched_check raises, on every replay (each
+    # replay resets the counters and the flag).  A list captured with the
+    # default budget then runs to the oracle's result.
+    say("queue bounded wait")
+    monkeypatch.setenv("KX_BATCHED", "queue")
+    systems = [((50, 50, 50), 0.3, 0.106, 16, 12, 97)]
+    monkeypatch.setenv("KX_QUEUE_SPIN", "0")
+    plans, tasks = _gamma_tasks(kx, "fp64", systems)
+    try:
+        gave_up = 0
+        for rep in range(3):
+            kx.exx_apply_batched(tasks)
+            try:
+                kx.kx_batched_check()
+            except kx.KronxError as e:
+                assert "gave up" in str(e)
+                gave_up += 1
+        assert gave_up == 3
+    finally:
+        for p in plans:
+            p.destroy()
+    monkeypatch.delenv("KX_QUEUE_SPIN")
+    ora = _oracle_systems("fp64", systems)
+    plans, tasks = _gamma_tasks(kx, "fp64", systems)
+    try:
+        kx.exx_apply_batched(tasks)
+        kx.kx_batched_check()
+        torch.cuda.synchronize()
+        assert kx.kx_batched_schedule()[2] == 1
+        for t, (W, E, _) in zip(tasks, ora):
+            assert rel_fro(to_host(t["vx"]), W) < 1e-12
+            assert abs(float(t["ex"][0]) - E) < 1e-12 * abs(E)
+    finally:
+        for p in plans:
+            p.destroy()
