@@ -311,14 +311,14 @@ int tuned_blocks(const kx_plan p, int pass) {
 }
 // Launch variant bits of pass `pass` (bit 0: alternative occupancy target;
 // bit 1: transposed mode-2 product, passes A and C; bit 2: eigenvector
-// matrices resident in LDS, passes B and C; bit 3: register hand-off,
-// passes B and C) for the FP64/FP32 real kernels; the other kernel families have one
+// matrices resident in LDS, passes B and C; bit 3: register hand-off, all
+// passes) for the FP64/FP32 real kernels; the other kernel families have one
 // variant.
 int tuned_variant(const kx_plan p, int pass, int variant) {
   const bool real_mfma = !p->cplx && (p->prec == KX_PREC_FP64 || p->prec == KX_PREC_FP32);
   if (!real_mfma) return variant;
   const int bits = p->tune_tv[pass];
-  if ((bits & 8) && pass != 0) return variant | kx::TUNE_RH;
+  if (bits & 8) return variant | kx::TUNE_RH;
   if ((bits & 4) && pass != 0) return variant | kx::TUNE_VL;
   if (bits & 1) variant |= kx::TUNE_ALT;
   if ((bits & 2) && pass != 1) variant |= kx::TUNE_TR;

@@ -45,6 +45,13 @@ struct QShape {
   static constexpr size_t elems = m1 > m2 ? m1 : m2;  // LDS elements of T
 };
 
+// Orientation of the mode-2 product in the queue's slice passes: the
+// transposed one for FP32 (at 120^3 FP32 pass A runs 207 ms per 64-band step
+// transposed against 301 ms direct, pass C 354 against 477), the direct one
+// for FP64, where the transposed one is the slower.
+template <typename T>
+constexpr bool kQTr2 = sizeof(T) == 4;
+
 // The fixed-order E_x reduction of k_ex_finalize (256 partial sums, then a
 // binary tree) with any block width.
 __device__ __forceinline__ void ex_finalize_body(const QFin& f, double* red256) {
@@ -117,13 +124,13 @@ k_queue(QueueArgs q) {
     const QTicket d = q.tickets[tk];
     switch (d.kind) {
       case QK_REAL_A:
-        slice_fwd_body<T, NKR, 0, true, true>(q.sa[d.arg], none, d.vb, d.vg, lds);
+        slice_fwd_body<T, NKR, 0, true, true, false, kQTr2<T>>(q.sa[d.arg], none, d.vb, d.vg, lds);
         break;
       case QK_REAL_B:
         pencil_body<T, NKR, true, true, true>(q.pa[d.arg], none, d.vb, d.vg, lds);
         break;
       case QK_REAL_C:
-        slice_inv_body<T, NKR, true, true, true>(q.ca[d.arg], none, d.vb, d.vg, lds, red);
+        slice_inv_body<T, NKR, true, true, true, false, kQTr2<T>>(q.ca[d.arg], none, d.vb, d.vg, lds, red);
         break;
       case QK_CPLX_A:
         slice_fwd_c_body<T, NKC, 0>(q.sa[d.arg], none, d.vb, d.vg, lds, lds + Sh::lc_slice);
