@@ -312,10 +312,11 @@ int tuned_blocks(const kx_plan p, int pass) {
 // Launch variant bits of pass `pass` (bit 0: alternative occupancy target;
 // bit 1: transposed mode-2 product, passes A and C; bit 2: eigenvector
 // matrices resident in LDS, passes B and C; bit 3: register hand-off, all
-// passes) for the FP64/FP32 real kernels; the other kernel families have one
-// variant.
+// passes) for the FP64/FP32 real kernels; the complex kernels take bit 0
+// (a higher occupancy target), the split-BF16 kernels have one variant.
 int tuned_variant(const kx_plan p, int pass, int variant) {
   const bool real_mfma = !p->cplx && (p->prec == KX_PREC_FP64 || p->prec == KX_PREC_FP32);
+  if (p->cplx) return (p->tune_tv[pass] & 1) ? (variant | kx::TUNE_ALT) : variant;
   if (!real_mfma) return variant;
   const int bits = p->tune_tv[pass];
   if (bits & 8) return variant | kx::TUNE_RH;
@@ -357,8 +358,8 @@ hipError_t launch_pass_a(kx_plan p, int variant, const kx::SliceArgs& A0, int64_
   using namespace kx;
   const int mb = tuned_blocks(p, 0);
   const SliceArgs A = kernel_args_a(p, A0);
-  if (p->cplx) return launch_slice_fwd_c(p->prec == KX_PREC_FP64, p->nk12, variant, A, items, mb, s, tt);
   if (variant == SF_PAIR12) variant = tuned_variant(p, 0, variant);
+  if (p->cplx) return launch_slice_fwd_c(p->prec == KX_PREC_FP64, p->nk12, variant, A, items, mb, s, tt);
   if (p->prec == KX_PREC_FP64) return launch_slice_fwd_f64(p->nk12, variant, A, items, mb, s, tt);
   if (p->prec == KX_PREC_FP32) return launch_slice_fwd_f32(p->nk12, variant, A, items, mb, s, tt);
   return launch_slice_fwd_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, A, items, mb, p->bf_vps12,
@@ -370,7 +371,7 @@ hipError_t launch_pass_b(kx_plan p, const kx::PencilArgs& B0, hipStream_t s,
   using namespace kx;
   const int mb = tuned_blocks(p, 1), v = tuned_variant(p, 1, PC_FSI);
   const PencilArgs B = kernel_args_b(p, B0);
-  if (p->cplx) return launch_pencil_c(p->prec == KX_PREC_FP64, p->nk3, B, mb, s, tt, items);
+  if (p->cplx) return launch_pencil_c(p->prec == KX_PREC_FP64, p->nk3, v, B, mb, s, tt, items);
   if (p->prec == KX_PREC_FP64) return launch_pencil_f64(p->nk3, v, B, mb, s, tt, items);
   if (p->prec == KX_PREC_FP32) return launch_pencil_f32(p->nk3, v, B, mb, s, tt, items);
   return launch_pencil_bf(bf_spl(p), p->bf_nt3, B, mb, p->bf_vps3, p->bf_kp3, s, tt, items);
@@ -381,8 +382,8 @@ hipError_t launch_pass_c(kx_plan p, int variant, const kx::AccArgs& C0, int64_t 
   using namespace kx;
   const int mb = tuned_blocks(p, 2);
   const AccArgs C = kernel_args_c(p, C0);
-  if (p->cplx) return launch_slice_inv_c(p->prec == KX_PREC_FP64, p->nk12, variant, C, items, mb, s, tt);
   if (variant == SI_ACC12) variant = tuned_variant(p, 2, variant);
+  if (p->cplx) return launch_slice_inv_c(p->prec == KX_PREC_FP64, p->nk12, variant, C, items, mb, s, tt);
   if (p->prec == KX_PREC_FP64) return launch_slice_inv_f64(p->nk12, variant, C, items, mb, s, tt);
   if (p->prec == KX_PREC_FP32) return launch_slice_inv_f32(p->nk12, variant, C, items, mb, s, tt);
   return launch_slice_inv_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, C, items, mb, p->bf_vps12,
@@ -1177,7 +1178,7 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
   static const int cand[][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {0, 4}, {1, 0}, {1, 1}, {1, 2},
                                 {1, 3}, {1, 4}, {2, 0}, {2, 1}, {2, 2}, {2, 3}, {2, 4}, {3, 0},
                                 {3, 1}, {3, 2}, {3, 3}, {3, 4}, {4, 0}, {4, 1}, {4, 2}, {8, 0}};
-  const int ncand = real_mfma ? 24 : 5;
+  const int ncand = real_mfma ? 24 : (p->cplx ? 10 : 5);
   hipEvent_t ev[4];
   for (int i = 0; i < 4; ++i) hipEventCreate(&ev[i]);
   float best[3] = {1e30f, 1e30f, 1e30f};

@@ -49,8 +49,11 @@ hipError_t cfwd(int variant, const SliceArgs& a, int64_t items, int max_blocks, 
     return hipErrorInvalidValue;
   } else {
     constexpr int TH = CTiles<NK>::THREADS;
-    void (*k)(SliceArgs, TaskTab) = tt.ntasks ? k_slice_fwd_c<T, NK, 0, true>
-                                    : variant == SF_PAIR12 ? k_slice_fwd_c<T, NK, 0> : k_slice_fwd_c<T, NK, 1>;
+    const bool alt = variant & TUNE_ALT;
+    void (*k)(SliceArgs, TaskTab) =
+        tt.ntasks ? (alt ? k_slice_fwd_c<T, NK, 0, true, true> : k_slice_fwd_c<T, NK, 0, true>)
+        : (variant & ~TUNE_ALT) == SF_PAIR12 ? (alt ? k_slice_fwd_c<T, NK, 0, false, true> : k_slice_fwd_c<T, NK, 0>)
+                                             : k_slice_fwd_c<T, NK, 1>;
     if (items <= 0) return hipSuccess;
     int64_t cap = (int64_t)c_resident(k, TH) * device_cu_count();
     if (max_blocks > 0) cap = std::min<int64_t>(cap, max_blocks);
@@ -60,12 +63,15 @@ hipError_t cfwd(int variant, const SliceArgs& a, int64_t items, int max_blocks, 
 }
 
 template <typename T, int NK>
-hipError_t cpencil(const PencilArgs& a, int max_blocks, hipStream_t s, const TaskTab& tt, int64_t items) {
+hipError_t cpencil(int variant, const PencilArgs& a, int max_blocks, hipStream_t s, const TaskTab& tt,
+                   int64_t items) {
   if constexpr ((size_t)2 * CTiles<NK>::P * 65 * sizeof(T) + 256 > 160 * 1024) {
     return hipErrorInvalidValue;
   } else {
   constexpr int TH = CTiles<NK>::THREADS;
-  void (*k)(PencilArgs, TaskTab) = tt.ntasks ? k_pencil_c<T, NK, true> : k_pencil_c<T, NK>;
+  const bool alt = variant & TUNE_ALT;
+  void (*k)(PencilArgs, TaskTab) = tt.ntasks ? (alt ? k_pencil_c<T, NK, true, true> : k_pencil_c<T, NK, true>)
+                                             : (alt ? k_pencil_c<T, NK, false, true> : k_pencil_c<T, NK>);
   int64_t cap = (int64_t)c_resident(k, TH) * device_cu_count();
   if (max_blocks > 0) cap = std::min<int64_t>(cap, max_blocks);
   if (tt.ntasks) {
@@ -88,8 +94,11 @@ hipError_t cinv(int variant, const AccArgs& a, int64_t items, int max_blocks, hi
     return hipErrorInvalidValue;
   } else {
     constexpr int TH = CTiles<NK>::THREADS;
-    void (*k)(AccArgs, TaskTab) = tt.ntasks ? k_slice_inv_c<T, NK, true, true>
-                                  : variant == SI_ACC12 ? k_slice_inv_c<T, NK, true> : k_slice_inv_c<T, NK, false>;
+    const bool alt = variant & TUNE_ALT;
+    void (*k)(AccArgs, TaskTab) =
+        tt.ntasks ? (alt ? k_slice_inv_c<T, NK, true, true, true> : k_slice_inv_c<T, NK, true, true>)
+        : (variant & ~TUNE_ALT) == SI_ACC12 ? (alt ? k_slice_inv_c<T, NK, true, false, true> : k_slice_inv_c<T, NK, true>)
+                                            : k_slice_inv_c<T, NK, false>;
     if (items <= 0) return hipSuccess;
     int64_t cap = (int64_t)c_resident(k, TH) * device_cu_count();
     if (max_blocks > 0) cap = std::min<int64_t>(cap, max_blocks);
@@ -108,7 +117,8 @@ hipError_t cinv(int variant, const AccArgs& a, int64_t items, int max_blocks, hi
 
 hipError_t launch_slice_fwd_c(bool f64, int nk, int variant, const SliceArgs& a, int64_t items,
                               int max_blocks, hipStream_t s, const TaskTab& tt) {
-  if (variant != SF_PAIR12 && variant != SF_LOAD12) return hipErrorInvalidValue;
+  const int base = variant & ~TUNE_ALT;
+  if (base != SF_PAIR12 && base != SF_LOAD12) return hipErrorInvalidValue;
   switch (nk) {
 #define C(n) \
   case n:    \
@@ -119,12 +129,13 @@ hipError_t launch_slice_fwd_c(bool f64, int nk, int variant, const SliceArgs& a,
   }
 }
 
-hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks, hipStream_t s,
+hipError_t launch_pencil_c(bool f64, int nk, int variant, const PencilArgs& a, int max_blocks, hipStream_t s,
                            const TaskTab& tt, int64_t items) {
   switch (nk) {
 #define C(n) \
   case n:    \
-    return f64 ? cpencil<double, n>(a, max_blocks, s, tt, items) : cpencil<float, n>(a, max_blocks, s, tt, items);
+    return f64 ? cpencil<double, n>(variant, a, max_blocks, s, tt, items) \
+               : cpencil<float, n>(variant, a, max_blocks, s, tt, items);
     KX_CNK_CASES(C)
 #undef C
     default: return hipErrorInvalidValue;
@@ -133,7 +144,8 @@ hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks
 
 hipError_t launch_slice_inv_c(bool f64, int nk, int variant, const AccArgs& a, int64_t items,
                               int max_blocks, hipStream_t s, const TaskTab& tt) {
-  if (variant != SI_ACC12 && variant != SI_ST12) return hipErrorInvalidValue;
+  const int base = variant & ~TUNE_ALT;
+  if (base != SI_ACC12 && base != SI_ST12) return hipErrorInvalidValue;
   switch (nk) {
 #define C(n) \
   case n:    \

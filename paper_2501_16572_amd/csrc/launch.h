@@ -74,7 +74,7 @@ inline int bf_lines(int nt) { return 16 * nt > bf_kp(nt) ? 16 * nt : bf_kp(nt); 
 // V arguments point at (re, im) planes, each P x P.
 hipError_t launch_slice_fwd_c(bool f64, int nk, int variant, const SliceArgs& a, int64_t items,
                               int max_blocks, hipStream_t s, const TaskTab& tt = kNoTasks);
-hipError_t launch_pencil_c(bool f64, int nk, const PencilArgs& a, int max_blocks, hipStream_t s,
+hipError_t launch_pencil_c(bool f64, int nk, int variant, const PencilArgs& a, int max_blocks, hipStream_t s,
                            const TaskTab& tt = kNoTasks, int64_t items = 0);
 hipError_t launch_slice_inv_c(bool f64, int nk, int variant, const AccArgs& a, int64_t items,
                               int max_blocks, hipStream_t s, const TaskTab& tt = kNoTasks);

@@ -496,12 +496,13 @@ def _forced_plan(kx, n, h, omega, prec, bits, bpc, psi_d, occ_d, cache):
 @pytest.mark.parametrize("n", [(40, 36, 44), (72, 68, 70)])
 def test_every_launch_variant_keeps_parity(kx, prec, n, tmp_path, monkeypatch):
     # variant bits: 1 occupancy target, 2 transposed mode-2 product (A, C),
-    # 4 eigenvector matrices in LDS (B, C), 8 register hand-off (B); each
-    # against the oracle, and the LDS and hand-off forms also in a grouped
-    # (task-table) batched launch of two plans
+    # 4 eigenvector matrices in LDS (B, C), 8 register hand-off (A, B, C);
+    # each against the oracle, and the LDS and hand-off forms also in a
+    # grouped (task-table) batched launch of two plans
     h, omega = (0.3, 0.3, 0.3), 0.106
     say("variants", prec, n)
     monkeypatch.setenv("KX_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    monkeypatch.setenv("KX_BATCHED", "rounds")  # the grouped form runs the tuned variants
     nb, no = 3, 2
     psi = random_orbitals(n, h, nb, seed=97)
     g = fermi_occupations(nb, no, 0.01, seed=97)
@@ -536,3 +537,52 @@ def test_every_launch_variant_keeps_parity(kx, prec, n, tmp_path, monkeypatch):
                     plan2.destroy()
         finally:
             plan.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_complex_occupancy_variant(kx, prec, tmp_path, monkeypatch):
+    # the complex kernels' occupancy variant (bit 1: at least 3 waves per
+    # SIMD), forced for all three passes of a Bloch plan, single and in a
+    # grouped batched launch, against the oracle at the same k - q
+    n, h = (40, 36, 44), (0.3, 0.3, 0.3)
+    say("complex occupancy variant", prec)
+    monkeypatch.setenv("KX_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    monkeypatch.setenv("KX_BATCHED", "rounds")
+    L = [n[d] * h[d] for d in range(3)]
+    kq = (2 * np.pi / L[0] * 0.25, -2 * np.pi / L[1] * 0.125, 2 * np.pi / L[2] * 0.5)
+    nb, no = 3, 2
+    psi = random_orbitals(n, h, nb, seed=99, kpt=kq, decay=2.0)
+    g = fermi_occupations(nb, no, 0.01, seed=99)
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    psi_in = psi if prec == "fp64" else psi.astype(np.complex64).astype(np.complex128)
+    S = KronSolver(n, h, BCP, 12, 0.0, kq)
+    W = vx_apply(psi_in[:no], g[:no], psi_in, S)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    psid = to_dev(psi_in, ct)
+    occ = to_dev(g[:no], torch.float64)
+    cache = tmp_path / "tune.txt"
+    p0 = kx.kron_setup(n, h, BCP, 12, 0.0, kq=kq, prec=prec, complex=True)
+    kx.kx_autotune(p0, psid[:no], occ, psid)
+    p0.destroy()
+    key = cache.read_text().split()[0]
+    with open(cache, "a") as f:
+        f.write(f"{key} 1 0 1 0 1 0\n")
+    plans = [kx.kron_setup(n, h, BCP, 12, 0.0, kq=kq, prec=prec, complex=True) for _ in range(2)]
+    try:
+        for p in plans:
+            kx.kx_autotune(p, psid[:no], occ, psid)
+            assert p.tuning()["A"] == (1, 0) and p.tuning()["C"] == (1, 0)
+        vx = torch.zeros(psid.shape, dtype=torch.complex128, device="cuda")
+        kx.exx_apply(plans[0], psid[:no], occ, psid, vx)
+        torch.cuda.synchronize()
+        assert rel_fro(to_host(vx), W) < tol
+        vxa = torch.zeros_like(vx)
+        vxb = torch.zeros_like(vx)
+        kx.exx_apply_batched([dict(plan=plans[0], psi=psid[:no], occ=occ, phi=psid, vx=vxa),
+                              dict(plan=plans[1], psi=psid[:no], occ=occ, phi=psid, vx=vxb)])
+        torch.cuda.synchronize()
+        assert kx.kx_batched_schedule()[3] == 2
+        assert rel_fro(to_host(vxa), W) < tol and rel_fro(to_host(vxb), W) < tol
+    finally:
+        for p in plans:
+            p.destroy()
