@@ -304,9 +304,10 @@ const char* kx_trace_name(int kind);
  * fastest candidate per pass in the plan (later exx_apply calls on any
  * stream use it).  Arguments as exx_apply; nothing the caller owns is written
  * (a private Vx buffer of one batch receives the results).  Synchronous;
- * costs two batches of device time per candidate (23 candidates for real
- * FP64/FP32 plans, 5 for complex and split-BF16 plans, which tune the
- * resident blocks per CU only), once per key.  If the environment variable
+ * costs two batches of device time per candidate (24 candidates for real
+ * FP64 plans, 28 for real FP32 plans, 10 for complex plans, 5 for
+ * split-BF16 plans, which tune the resident blocks per CU only), once per
+ * key.  If the environment variable
  * KX_TUNE_CACHE names a file, choices are read from and appended to it (one
  * line per key: arch, grid, precision, complex flag, n_occ), and a cached key
  * skips the timing. */
@@ -314,12 +315,17 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
                       const void* d_phi, int64_t ld_phi, int n_b, void* stream);
 
 /* kx_plan_tuning -- the plan's current launch configuration per fused pass:
- * out[2*i] = variant bits (bit 0: alternative occupancy target; bit 1, passes
- * A and C: mode-2 product computed transposed, x1 along the MFMA columns;
- * bit 2, passes B and C: eigenvector matrices resident in LDS, the next work
- * item's data prefetched into registers; it overrides bits 0 and 1),
- * out[2*i+1] = resident blocks per CU (0 = as many as fit), for passes
- * i = A, B, C; out[6] = 1 if it came from kx_autotune (timed or cached). */
+ * out[2*i] = variant bits (bit 0: alternative occupancy target, real and
+ * complex plans; bit 1, passes A and C: mode-2 product computed transposed,
+ * x1 along the MFMA columns; bit 2, passes B and C: eigenvector matrices
+ * resident in LDS, the next work item's data prefetched into registers; it
+ * overrides bits 0 and 1; bit 3: register hand-off, the second product of
+ * the pass taking the first one's accumulators as its operand; it
+ * overrides bits 0-2; bit 4, real FP32 plans: the pass runs the six-product
+ * split-BF16 kernel, which keeps the FP32 accuracy class; it overrides the
+ * others), out[2*i+1] = resident blocks per CU (0 = as many as fit), for
+ * passes i = A, B, C; out[6] = 1 if it came from kx_autotune (timed or
+ * cached). */
 kx_status kx_plan_tuning(kx_plan p, int out[7]);
 
 /* ---- Adaptively compressed exchange (ACE) --------------------------------

@@ -305,6 +305,14 @@ kx_status check_exx_args(kx_plan p, const void* psi, int64_t ld_psi, int n_occ, 
 // Precision dispatch of the three fused passes.
 bool is_bf(const kx_plan p) { return p->prec == KX_PREC_BF16X3 || p->prec == KX_PREC_BF16X6; }
 int bf_spl(const kx_plan p) { return p->prec == KX_PREC_BF16X3 ? 2 : 3; }
+// Pass `pass` of plan p runs the split-BF16 kernels: every pass of a
+// split-BF16 plan, and a pass of a real FP32 plan whose tuned variant has
+// bit 16 -- the six-product split, in the accuracy class of FP32 (both keep
+// the pair intermediates in FP32 storage and accumulate in FP32), which is
+// the faster kernel on some passes.
+bool pass_bf(const kx_plan p, int pass) {
+  return is_bf(p) || (!p->cplx && p->prec == KX_PREC_FP32 && (p->tune_tv[pass] & 16));
+}
 
 int tuned_blocks(const kx_plan p, int pass) {
   return p->tune_bpc[pass] > 0 ? p->tune_bpc[pass] * kx::device_cu_count() : p->max_blocks;
@@ -326,24 +334,24 @@ int tuned_variant(const kx_plan p, int pass, int variant) {
   return variant;
 }
 
-// The argument structs as the kernels of plan p read them: split-BF16 plans
-// take the split eigenvector parts in place of the FP64 matrices.
-kx::SliceArgs kernel_args_a(const kx_plan p, kx::SliceArgs A) {
-  if (is_bf(p) && !p->cplx) {
+// The argument structs as the kernels of plan p read them: the split-BF16
+// kernels (bf) take the split eigenvector parts in place of the matrices.
+kx::SliceArgs kernel_args_a(const kx_plan p, kx::SliceArgs A, bool bf) {
+  if (bf && !p->cplx) {
     A.V1 = p->dVbf[0][0];
     A.V2 = p->dVbf[1][0];
   }
   return A;
 }
-kx::PencilArgs kernel_args_b(const kx_plan p, kx::PencilArgs B) {
-  if (is_bf(p) && !p->cplx) {
+kx::PencilArgs kernel_args_b(const kx_plan p, kx::PencilArgs B, bool bf) {
+  if (bf && !p->cplx) {
     B.V3 = p->dVbf[2][0];
     B.V3T = p->dVbf[2][1];
   }
   return B;
 }
-kx::AccArgs kernel_args_c(const kx_plan p, kx::AccArgs C) {
-  if (is_bf(p) && !p->cplx) {
+kx::AccArgs kernel_args_c(const kx_plan p, kx::AccArgs C, bool bf) {
+  if (bf && !p->cplx) {
     C.V1 = p->dVbf[0][1];
     C.V2 = p->dVbf[1][1];
   }
@@ -357,11 +365,13 @@ hipError_t launch_pass_a(kx_plan p, int variant, const kx::SliceArgs& A0, int64_
                          const kx::TaskTab& tt = kx::kNoTasks) {
   using namespace kx;
   const int mb = tuned_blocks(p, 0);
-  const SliceArgs A = kernel_args_a(p, A0);
-  if (variant == SF_PAIR12) variant = tuned_variant(p, 0, variant);
+  const bool bf = pass_bf(p, 0);
+  const SliceArgs A = kernel_args_a(p, A0, bf);
+  if (bf) variant &= ~(kx::TUNE_ALT | kx::TUNE_TR | kx::TUNE_VL | kx::TUNE_RH);
+  else if (variant == SF_PAIR12) variant = tuned_variant(p, 0, variant);
   if (p->cplx) return launch_slice_fwd_c(p->prec == KX_PREC_FP64, p->nk12, variant, A, items, mb, s, tt);
-  if (p->prec == KX_PREC_FP64) return launch_slice_fwd_f64(p->nk12, variant, A, items, mb, s, tt);
-  if (p->prec == KX_PREC_FP32) return launch_slice_fwd_f32(p->nk12, variant, A, items, mb, s, tt);
+  if (!bf && p->prec == KX_PREC_FP64) return launch_slice_fwd_f64(p->nk12, variant, A, items, mb, s, tt);
+  if (!bf && p->prec == KX_PREC_FP32) return launch_slice_fwd_f32(p->nk12, variant, A, items, mb, s, tt);
   return launch_slice_fwd_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, A, items, mb, p->bf_vps12,
                              p->bf_kp12, s, tt);
 }
@@ -370,10 +380,11 @@ hipError_t launch_pass_b(kx_plan p, const kx::PencilArgs& B0, hipStream_t s,
                          const kx::TaskTab& tt = kx::kNoTasks, int64_t items = 0) {
   using namespace kx;
   const int mb = tuned_blocks(p, 1), v = tuned_variant(p, 1, PC_FSI);
-  const PencilArgs B = kernel_args_b(p, B0);
+  const bool bf = pass_bf(p, 1);
+  const PencilArgs B = kernel_args_b(p, B0, bf);
   if (p->cplx) return launch_pencil_c(p->prec == KX_PREC_FP64, p->nk3, v, B, mb, s, tt, items);
-  if (p->prec == KX_PREC_FP64) return launch_pencil_f64(p->nk3, v, B, mb, s, tt, items);
-  if (p->prec == KX_PREC_FP32) return launch_pencil_f32(p->nk3, v, B, mb, s, tt, items);
+  if (!bf && p->prec == KX_PREC_FP64) return launch_pencil_f64(p->nk3, v, B, mb, s, tt, items);
+  if (!bf && p->prec == KX_PREC_FP32) return launch_pencil_f32(p->nk3, v, B, mb, s, tt, items);
   return launch_pencil_bf(bf_spl(p), p->bf_nt3, B, mb, p->bf_vps3, p->bf_kp3, s, tt, items);
 }
 
@@ -381,11 +392,13 @@ hipError_t launch_pass_c(kx_plan p, int variant, const kx::AccArgs& C0, int64_t 
                          const kx::TaskTab& tt = kx::kNoTasks) {
   using namespace kx;
   const int mb = tuned_blocks(p, 2);
-  const AccArgs C = kernel_args_c(p, C0);
-  if (variant == SI_ACC12) variant = tuned_variant(p, 2, variant);
+  const bool bf = pass_bf(p, 2);
+  const AccArgs C = kernel_args_c(p, C0, bf);
+  if (bf) variant &= ~(kx::TUNE_ALT | kx::TUNE_TR | kx::TUNE_VL | kx::TUNE_RH);
+  else if (variant == SI_ACC12) variant = tuned_variant(p, 2, variant);
   if (p->cplx) return launch_slice_inv_c(p->prec == KX_PREC_FP64, p->nk12, variant, C, items, mb, s, tt);
-  if (p->prec == KX_PREC_FP64) return launch_slice_inv_f64(p->nk12, variant, C, items, mb, s, tt);
-  if (p->prec == KX_PREC_FP32) return launch_slice_inv_f32(p->nk12, variant, C, items, mb, s, tt);
+  if (!bf && p->prec == KX_PREC_FP64) return launch_slice_inv_f64(p->nk12, variant, C, items, mb, s, tt);
+  if (!bf && p->prec == KX_PREC_FP32) return launch_slice_inv_f32(p->nk12, variant, C, items, mb, s, tt);
   return launch_slice_inv_bf(bf_spl(p), p->bf_nt12, variant & ~kx::TUNE_ALT, C, items, mb, p->bf_vps12,
                              p->bf_kp12, s, tt);
 }
@@ -404,7 +417,7 @@ int64_t pass_c_grid(kx_plan p) {
 // 2 = C) have equal keys: same kernel family, element type, tile count and
 // tuned variant.
 std::array<int, 6> launch_key(const kx_plan p, int pass) {
-  const int fam = p->cplx ? 2 : (is_bf(p) ? 1 : 0);
+  const int fam = p->cplx ? 2 : (pass_bf(p, pass) ? 1 : 0);
   const int tiles = fam == 1 ? (pass == 1 ? p->bf_nt3 : p->bf_nt12) : (pass == 1 ? p->nk3 : p->nk12);
   const int vps = fam == 1 ? (pass == 1 ? p->bf_vps3 : p->bf_vps12) : 0;
   return {fam, p->prec, tiles, tuned_variant(p, pass, 0), vps, tuned_blocks(p, pass)};
@@ -794,7 +807,9 @@ kx_status kron_setup(const int n[3], const double h[3], const int bc[3], int fd_
   }
   hipError_t e = hipMalloc((void**)&p->d_f, p->f.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(p->d_f, p->f.data(), p->f.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (e == hipSuccess && (prec == KX_PREC_BF16X3 || prec == KX_PREC_BF16X6)) {
+  // split-BF16 parts: the split plans' matrices, and for real FP32 plans the
+  // six-product parts their passes may run (tuned variant bit 16)
+  if (e == hipSuccess && (prec == KX_PREC_BF16X3 || prec == KX_PREC_BF16X6 || (prec == KX_PREC_FP32 && !p->cplx))) {
     const int parts = prec == KX_PREC_BF16X3 ? 2 : 3;
     p->bf_nt12 = kx::bf_nt(std::max(n[0], n[1]));
     p->bf_nt3 = kx::bf_nt(n[2]);
@@ -1172,13 +1187,15 @@ kx_status kx_autotune(kx_plan p, const void* d_psi, int64_t ld_psi, int n_occ, c
     (void)hipGetLastError();
     return fail(KX_ENOMEM, "kx_autotune: sample Vx buffer");
   }
-  // candidates: (occupancy variant, resident blocks per CU; 0 = all that fit)
-  // (variant bits, resident blocks per CU); the variant bits exist for the
-  // FP64/FP32 real kernels only
+  // candidates: (variant bits, resident blocks per CU; 0 = all that fit).
+  // The first 24 serve the FP64/FP32 real kernels, the last 4 (the
+  // six-product split-BF16 kernels) real FP32 plans only; complex plans take
+  // the first 10 (bit 0 only), split-BF16 plans the first 5.
   static const int cand[][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {0, 4}, {1, 0}, {1, 1}, {1, 2},
                                 {1, 3}, {1, 4}, {2, 0}, {2, 1}, {2, 2}, {2, 3}, {2, 4}, {3, 0},
-                                {3, 1}, {3, 2}, {3, 3}, {3, 4}, {4, 0}, {4, 1}, {4, 2}, {8, 0}};
-  const int ncand = real_mfma ? 24 : (p->cplx ? 10 : 5);
+                                {3, 1}, {3, 2}, {3, 3}, {3, 4}, {4, 0}, {4, 1}, {4, 2}, {8, 0},
+                                {16, 0}, {16, 1}, {16, 2}, {16, 3}};
+  const int ncand = real_mfma ? (p->prec == KX_PREC_FP32 ? 28 : 24) : (p->cplx ? 10 : 5);
   hipEvent_t ev[4];
   for (int i = 0; i < 4; ++i) hipEventCreate(&ev[i]);
   float best[3] = {1e30f, 1e30f, 1e30f};
@@ -1393,9 +1410,10 @@ QueueBuild build_queue(const kx_task* tasks, const std::vector<std::vector<SubTa
       const double* hi = lo + (size_t)(st.cur - 1) * t.ld_vx * vxw + (size_t)p->N * vxw;
       const BatchArgs ba = batch_args(p, t.d_psi, t.ld_psi, t.n_occ, t.d_occ, t.d_phi, t.ld_phi, t.d_vx, t.ld_vx,
                                       t.d_ex != nullptr, st.n0, st.cur);
-      q.sa.push_back(kernel_args_a(p, ba.A));
-      q.pa.push_back(kernel_args_b(p, ba.B));
-      q.ca.push_back(kernel_args_c(p, ba.C));
+      // the queue runs the FP64 / FP32 bodies of every pass
+      q.sa.push_back(kernel_args_a(p, ba.A, false));
+      q.pa.push_back(kernel_args_b(p, ba.B, false));
+      q.ca.push_back(kernel_args_c(p, ba.C, false));
       fin_index.push_back(t.d_ex ? (int)q.fa.size() : -1);
       if (t.d_ex) q.fa.push_back(kx::QFin{p->d_part, st.cur, p->n[2], t.d_gphi + st.n0, p->dV, t.d_ex});
       cplx.push_back(p->cplx);
@@ -1661,15 +1679,15 @@ kx_status exx_apply_batched(const kx_task* tasks, int ntasks, void* stream) {
         int64_t items = 0;
         char* dst = h.data() + gl.args_off + j * arg_size(gl.pass);
         if (gl.pass == 0) {
-          const kx::SliceArgs a = kernel_args_a(p, ba.A);
+          const kx::SliceArgs a = kernel_args_a(p, ba.A, pass_bf(p, 0));
           std::memcpy(dst, &a, sizeof(a));
           items = (int64_t)ba.A.npairs * p->n[2];
         } else if (gl.pass == 1) {
-          const kx::PencilArgs b = kernel_args_b(p, ba.B);
+          const kx::PencilArgs b = kernel_args_b(p, ba.B, pass_bf(p, 1));
           std::memcpy(dst, &b, sizeof(b));
           items = (int64_t)ba.B.nchunks * ba.B.npairs;
         } else {
-          const kx::AccArgs c = kernel_args_c(p, ba.C);
+          const kx::AccArgs c = kernel_args_c(p, ba.C, pass_bf(p, 2));
           std::memcpy(dst, &c, sizeof(c));
           items = (int64_t)st.cur * p->n[2];
         }

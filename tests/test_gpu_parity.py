@@ -496,9 +496,10 @@ def _forced_plan(kx, n, h, omega, prec, bits, bpc, psi_d, occ_d, cache):
 @pytest.mark.parametrize("n", [(40, 36, 44), (72, 68, 70)])
 def test_every_launch_variant_keeps_parity(kx, prec, n, tmp_path, monkeypatch):
     # variant bits: 1 occupancy target, 2 transposed mode-2 product (A, C),
-    # 4 eigenvector matrices in LDS (B, C), 8 register hand-off (A, B, C);
-    # each against the oracle, and the LDS and hand-off forms also in a
-    # grouped (task-table) batched launch of two plans
+    # 4 eigenvector matrices in LDS (B, C), 8 register hand-off (A, B, C),
+    # 16 split-BF16 six-product kernels (FP32 plans); each against the
+    # oracle, and the LDS, hand-off and split forms also in a grouped
+    # (task-table) batched launch of two plans
     h, omega = (0.3, 0.3, 0.3), 0.106
     say("variants", prec, n)
     monkeypatch.setenv("KX_TUNE_CACHE", str(tmp_path / "tune.txt"))
@@ -514,7 +515,7 @@ def test_every_launch_variant_keeps_parity(kx, prec, n, tmp_path, monkeypatch):
     psid = to_dev(psi_in, dt)
     occ = to_dev(g[:no], torch.float64)
     cache = tmp_path / "tune.txt"
-    for bits in (0, 1, 2, 3, 4, 8):
+    for bits in (0, 1, 2, 3, 4, 8) + ((16,) if prec == "fp32" else ()):
         plan = _forced_plan(kx, n, h, omega, prec, bits, 0, psid, occ, cache)
         try:
             vx = torch.zeros(psid.shape, dtype=torch.float64, device="cuda")
@@ -522,7 +523,7 @@ def test_every_launch_variant_keeps_parity(kx, prec, n, tmp_path, monkeypatch):
             torch.cuda.synchronize()
             err = rel_fro(to_host(vx), W)
             assert err < tol, (bits, err)
-            if bits in (4, 8):
+            if bits in (4, 8, 16):
                 plan2 = _forced_plan(kx, n, h, omega, prec, bits, 0, psid, occ, cache)
                 try:
                     vxa = torch.zeros_like(vx)
