@@ -400,6 +400,36 @@ def run_batched(kx, torch, np, cfg, args):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         kx.kx_batched_check()
+        # the other form of the same call, timed the same way (its own
+        # capture): the grouped rounds of tuned kernels, or the work queue
+        alt = None
+        if not args.no_alt_form:
+            other = "rounds" if sched[2] == 1 else "queue"
+            old_env = os.environ.get("KX_BATCHED")
+            os.environ["KX_BATCHED"] = other
+            try:
+                kx.exx_apply_batched(tasks)
+                torch.cuda.synchronize()
+                alt_sched = kx.kx_batched_schedule()
+                for _ in range(args.warmup):
+                    kx.exx_apply_batched(tasks)
+                a0 = torch.cuda.Event(enable_timing=True)
+                a1 = torch.cuda.Event(enable_timing=True)
+                a0.record(stream)
+                for _ in range(args.steps):
+                    kx.exx_apply_batched(tasks)
+                a1.record(stream)
+                torch.cuda.synchronize()
+                alt_ms = a0.elapsed_time(a1)
+                alt = dict(form=other, solves_per_s=round(solves * args.steps / (alt_ms / 1e3), 2),
+                           ms_per_step=round(alt_ms / args.steps, 4),
+                           useful_tflops=round(flops * args.steps / (alt_ms / 1e3) / 1e12, 3),
+                           schedule=dict(zip(("rounds", "batches", "launches", "widest_launch"), alt_sched)))
+            finally:
+                if old_env is None:
+                    os.environ.pop("KX_BATCHED", None)
+                else:
+                    os.environ["KX_BATCHED"] = old_env
         # one more replay on zeroed outputs: the sampled rows against the
         # oracle, and the Vx of k-point 0 for ACE
         for v in vx_k + vx_g:
@@ -450,7 +480,9 @@ def run_batched(kx, torch, np, cfg, args):
                    "systems": [list(sy["n"]) for sy in systems],
                    "pair_solves_per_step": solves},
         "useful_tflops": round(achieved, 3),
+        "form": "work queue (one launch per replay)" if queue else "grouped rounds",
         "schedule": dict(zip(("rounds", "batches", "launches", "widest_launch"), sched)),
+        "other_form": alt,
         "rel_err_sampled_vs_oracle": sample_err,
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -567,6 +599,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch configuration instead of kx_autotune's choice")
     ap.add_argument("--no-ace", action="store_true", help="skip the ACE construction/application timing")
+    ap.add_argument("--no-alt-form", action="store_true",
+                    help="batched workloads: skip timing the other form of exx_apply_batched")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line: time per solve vs right-hand sides per call")
     ap.add_argument("--compare", action="store_true",
