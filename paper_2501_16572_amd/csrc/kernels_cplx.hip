@@ -4,8 +4,9 @@
 // eigenvectors (Sec. II; Eq. (FinalRepfL) with V^{*T}), the pair density is
 // conj(psi_mq) (.) phi_nk (Eq. (Poisson)), the forward transform uses
 // V1^{*T}, V2^*, V3^* and the inverse V1, V2^T, V3^T (Sec. II.A).  Each
-// complex mode product is four real MFMA products on (re, im) planes:
-//   (Ar + i Ai)(Br + i Bi) = (Ar Br - Ai Bi) + i (Ar Bi + Ai Br).
+// complex mode product is three real MFMA products on (re, im) planes:
+//   (Ar + i Ai)(Br + i Bi) = (P1 - P2) + i (P3 - P1 - P2),
+//   P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi).
 // Element type T: double (complex128 data, v_mfma_f64_16x16x4) or float
 // (complex64 data, v_mfma_f32_16x16x4 with FP32 accumulation).  Global data
 // is interleaved (re, im); LDS holds separate re / im planes.  The f table,
