@@ -534,6 +534,19 @@ def test_every_launch_variant_keeps_parity(kx, prec, n, tmp_path, monkeypatch):
                     assert kx.kx_batched_schedule()[3] == 2
                     assert rel_fro(to_host(vxa), W) < tol
                     assert rel_fro(to_host(vxb), W) < tol
+                    if bits == 16:
+                        # the work queue runs its own FP32 bodies whatever the
+                        # tuning says
+                        monkeypatch.setenv("KX_BATCHED", "queue")
+                        vxa.zero_()
+                        vxb.zero_()
+                        kx.exx_apply_batched([dict(plan=plan, psi=psid[:no], occ=occ, phi=psid, vx=vxa),
+                                              dict(plan=plan2, psi=psid[:no], occ=occ, phi=psid, vx=vxb)])
+                        kx.kx_batched_check()
+                        assert kx.kx_batched_schedule()[2] == 1
+                        assert rel_fro(to_host(vxa), W) < tol
+                        assert rel_fro(to_host(vxb), W) < tol
+                        monkeypatch.setenv("KX_BATCHED", "rounds")
                 finally:
                     plan2.destroy()
         finally:
