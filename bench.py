@@ -65,6 +65,16 @@ def measured_traffic(workload, form, kernel):
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
+def calibrate_copy(torch):
+    """A 1 GiB fill and a 1 GiB device copy before the workload: the
+    reference dispatches that scale FETCH_SIZE / WRITE_SIZE to bytes."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -337,10 +347,22 @@ def run_batched(kx, torch, np, cfg, args):
     if not args.no_cpu:
         log("oracle sample on the host cores")
         W_oracle, cpu = cpu_baseline_batched(cfg, kpart, systems, prec)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
     rdt = torch.float64 if prec == "fp64" else torch.float32
     cdt = torch.complex128 if prec == "fp64" else torch.complex64
     plans, tasks, tune_args = {}, [], {}
     solves, flops = 0, 0.0
+    # algorithmic HBM bytes per replay: every pair intermediate written by
+    # pass A, read and written by pass B, read by pass C; orbitals read once
+    # by pass A and once by pass C; Vx read and written once
+    eb = 8 if prec == "fp64" else 4
+    alg_bytes = 0.0
+
+    def task_bytes(n, n_b, n_occ, cplx):
+        e = eb * (2 if cplx else 1)
+        return (4.0 * n_b * n_occ * n * e + 2.0 * (n_b + n_occ) * n * e
+                + 2.0 * n_b * n * (16 if cplx else 8))
     nk = len(kpart["kpts"])
     try:
         psi_k = [torch.from_numpy(p).to("cuda", cdt) for p in kpart["psi"]]
@@ -364,6 +386,7 @@ def run_batched(kx, torch, np, cfg, args):
                 tune_args.setdefault(key, t)
                 solves += psi_k[ik].shape[0] * n_occ
                 flops += 4.0 * (4.0 * N * sum(nkq)) * psi_k[ik].shape[0] * n_occ
+                alg_bytes += task_bytes(N, psi_k[ik].shape[0], n_occ, True)
         vx_g = []
         for i, sy in enumerate(systems):
             key = ("g", i)
@@ -379,6 +402,7 @@ def run_batched(kx, torch, np, cfg, args):
             Ns = sy["n"][0] * sy["n"][1] * sy["n"][2]
             solves += psid.shape[0] * sy["n_occ"]
             flops += 4.0 * Ns * sum(sy["n"]) * psid.shape[0] * sy["n_occ"]
+            alg_bytes += task_bytes(Ns, psid.shape[0], sy["n_occ"], False)
         if not args.no_autotune:
             for key, t in tune_args.items():
                 kx.kx_autotune(t["plan"], t["psi"], t["occ"], t["phi"])
@@ -462,14 +486,19 @@ def run_batched(kx, torch, np, cfg, args):
     peak = PEAK_TFLOPS["fp64" if prec == "fp64" else "fp32"]
     achieved = flops * args.steps / t / 1e12
     roof = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                frac=round(achieved / peak, 4), traffic=None,
+                frac=round(achieved / peak, 4),
+                traffic=measured_traffic(args.workload, f"{prec}:queue", "k_queue") if queue else None,
+                traffic_unit="HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                algorithmic_bytes_per_launch=alg_bytes,
                 kernel="k_queue (work-queue launch: every pass of every batch)" if queue else
                 "whole replay (grouped-round form: several kernels)",
                 avg_launch_ms=round(ms / args.steps, 4), launches=args.steps,
                 note="algorithmic flops per launch = sum over tasks of targets x occupied x "
                      "4 N (n1 + n2 + n3) (x4 for the complex k-point plans); launch duration from HIP "
                      "events on the launch stream around the replays, each a counter-reset kernel of "
-                     "a few microseconds and the queue launch")
+                     "a few microseconds and the queue launch; traffic = measured HBM bytes of the queue "
+                     "launch, algorithmic bytes = pair intermediates written by pass A, read and written by "
+                     "pass B, read by pass C, plus orbitals read by A and C and Vx read and written once")
     line = {
         "metric": METRIC, "value": round(solves * args.steps / t, 2), "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -653,11 +682,7 @@ def main():
         W_oracle, cpu = cpu_baseline(cfg, psi, g, n_occ, bands)
 
     if args.calibrate_copy:
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibrate_copy(torch)
     psi_d = torch.from_numpy(psi).cuda()
     g_d = torch.from_numpy(g).cuda()
     flops_per_solve = 4.0 * N * (n1 + n2 + n3)
