@@ -45,7 +45,8 @@ def _exx(plan, a):
     ("gphi", lambda a: a["gphi"].to(torch.float32), "gphi: dtype"),
     ("ex", lambda a: a["ex"].to(torch.float32), "ex: dtype"),
     ("ex", lambda a: torch.zeros(0, dtype=torch.float64), "ex: a contiguous"),
-    ("psi", lambda a: a["psi"].to(torch.complex64 if not a["psi"].is_complex() else torch.float32),
+    ("psi", lambda a: torch.zeros(a["psi"].shape,
+                                  dtype=torch.complex64 if not a["psi"].is_complex() else torch.float32),
      "psi: dtype"),
     ("phi", lambda a: a["phi"][:, : N - 1], "phi: expected"),
 ])
